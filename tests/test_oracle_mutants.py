@@ -1,0 +1,80 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a wrong sign, a dropped term, a transposed
+operand, a wrong index or exponent) in a copy of oracle/tfo.cpp, builds it on
+the CPU and runs a short battery of the same checks the pin tests make
+(accuracy against mpmath, special values).  Every mutant must fail the battery,
+and the unmodified source must pass it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mpref
+from paper_1502_05216_amd import workloads
+
+SRC = open(oracle.SRC).read()
+
+MUTANTS = {
+    "mul_td sign": ("return {pe.x0, fma(A.x1, c, pe.x1)};", "return {pe.x0, fma(A.x1, c, -pe.x1)};"),
+    "two_sum sign": ("return {s, da + db};", "return {s, da - db};"),
+    "mul_tt dropped term": ("fma(A.x0, B.x1, fma(A.x1, B.x0, pe.x1))", "fma(A.x1, B.x0, pe.x1)"),
+    "Horner dropped term": ("for (int j = K::N - 2; j >= 0; --j)", "for (int j = K::N - 2; j >= 1; --j)"),
+    "texp dropped z0*t1": ("T z1s = z0s * t1 + (s.v.x1 + (s.v.x0 - z0s));",
+                           "T z1s = (s.v.x1 + (s.v.x0 - z0s));"),
+    "Newton dropped s": ("add_tt(add_tt(mul_tt(a, s), a), s)", "add_tt(mul_tt(a, s), a)"),
+    "pexpm10 transposed": ("mul_tt(C, Tt));", "mul_tt(C, C));"),
+    "scaling sign": ("T z0s = ldexp(z0, -s.k);", "T z0s = ldexp(z0, s.k);"),
+    "texpm1 dropped +1": ("z1 = (z0 + T(1)) * t1", "z1 = z0 * t1"),
+    "expm1 scaled -1": ("two_sum(shi, -ldexp(T(1), -m))", "two_sum(shi, -ldexp(T(1), m))"),
+    "log dropped z1": ("Tw<T> a = {z.x0 - T(1), z.x1};               /* exact (Sterbenz) */",
+                       "Tw<T> a = {z.x0 - T(1), T(0)};"),
+    "n ln2 low part": ("mul_td(Tw<T>{T(K::LN2_HI()), T(K::LN2_LO())}, from_int<T>(n))",
+                       "mul_td(Tw<T>{T(K::LN2_HI()), T(0)}, from_int<T>(n))"),
+    "log table index": ("T r = fma(z, T(K::LOG_INVC()[i]), T(-1)); /* exact */",
+                        "T r = fma(z, T(K::LOG_INVC()[i ^ 1]), T(-1));"),
+    "exp table low part": ("T y = s + fma(s, p, T(K::S_LO()[j]));", "T y = s + fma(s, p, T(0));"),
+}
+
+
+def battery(o):
+    """True if the oracle build `o` passes a short version of the pins."""
+    thr = {"texp": (-98, -95), "texpm1": (-98, -95), "tlog": (-98, -93), "tlog1p": (-98, -93)}
+    for fn in ("texp", "texpm1", "tlog", "tlog1p"):
+        x0, x1 = workloads.twofold_inputs(fn, 400, np.float64, seed=5, edges=0.0)
+        z0, z1 = getattr(o, fn)(x0, x1)
+        rel = []
+        for a, b, c, d in zip(x0, x1, z0, z1):
+            v = mpref.exact(fn, a, b)
+            if v is None or abs(v) < 2.0 ** -969:
+                continue
+            if not np.isfinite(c) or not np.isfinite(d):
+                return False
+            rel.append(mpref.rel_error(c, d, v))
+        rel = np.array(rel)
+        if rel.mean() > 2.0 ** thr[fn][0] or rel.max() > 2.0 ** thr[fn][1]:
+            return False
+    for fn, name in (("exp", "exp1x"), ("expm1", "expm1_1x"), ("log", "log1x"),
+                     ("log1p", "log1p_1x")):
+        x, _ = workloads.twofold_inputs("t" + fn, 400, np.float64, seed=6, edges=0.0)
+        z = getattr(o, name)(x)
+        errs = [mpref.ulp_error(zi, mpref.exact(fn, xi), "D") for xi, zi in zip(x, z)
+                if mpref.exact(fn, xi) is not None and abs(float(mpref.exact(fn, xi))) > 2.0 ** -1022]
+        if max(errs) > 0.52 or np.mean(errs) > 0.3:
+            return False
+    return True
+
+
+def test_unmodified_source_passes(tmp_path):
+    path = oracle.build_variant(SRC, str(tmp_path / "libtfo_same.so"))
+    assert battery(oracle.variant(path))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    assert SRC.count(old) >= 1, name
+    path = oracle.build_variant(SRC.replace(old, new, 1), str(tmp_path / "libtfo_mut.so"))
+    assert not battery(oracle.variant(path)), name
