@@ -1,0 +1,103 @@
+/*
+ * twofold_hip.h -- C ABI of the MI355X twofold exp/log library
+ * (libtwofold_hip.so, HIP kernels for gfx950).
+ *
+ * A twofold x0 + x1 is a pair of IEEE numbers whose sum carries nearly twice
+ * the working precision.  The twofold functions of E. Latkin, "Twofold exp and
+ * log" (2015), return z0 + z1 ~ f(x0 + x1) where z0 is, bit for bit, the 1x
+ * function of x0 and z1 estimates the deviation f(x0 + x1) - z0 (sections
+ * "Twofold exponent: Method summary" and "Twofold logarithm: Newton
+ * inversion"; the plain C interface z0 = texp(x0, x1, &z1) of the section
+ * "C/C++ interface" becomes an elementwise call over arrays here).
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays are split: x0[i], x1[i] are the two parts of element i (SoA),
+ *    contiguous, n elements each.  All array pointers are DEVICE pointers
+ *    owned by the caller; the library keeps no reference after the call.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous: they enqueue work on `stream` and return.  Results are
+ *    visible after the stream is synchronised.  Execution faults surface at
+ *    that synchronisation, as usual for HIP.
+ *  - n == 0 returns TF_OK and enqueues nothing.  A NULL array pointer with
+ *    n > 0 returns TF_EINVAL and enqueues nothing (checked before any HIP
+ *    call).  No HIP device -> TF_ENODEV.  A failed launch -> TF_ELAUNCH.
+ *  - In-place use (z0 == x0 and z1 == x1) is allowed; any other overlap of
+ *    outputs with inputs is undefined.
+ *  - Numeric domain problems are not errors: they give NaN or infinities.
+ *    When z0 is NaN, z1 is NaN; when z0 is +-inf, z1 is +0.  A log whose
+ *    main part y0 is inside the domain while y0 + y1 is not returns a number
+ *    x0 and x1 = NaN (x1 = -inf when y0 + y1 is exactly the pole, +inf when it
+ *    is +inf) -- section "Logarithm: Algorithm summary".
+ *  - The functions are reentrant; the library holds no mutable state except
+ *    a per-device cache of the compute-unit count.
+ */
+#ifndef TWOFOLD_HIP_H
+#define TWOFOLD_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TF_OK = 0,
+    TF_EINVAL = 1,      /* invalid argument (NULL pointer with n > 0, bad descriptor) */
+    TF_ELAUNCH = 2,     /* kernel launch or HIP runtime call failed */
+    TF_ENOMEM = 3,      /* device allocation failed (batch plans only) */
+    TF_EUNSUPPORTED = 4,
+    TF_ENODEV = 5       /* no HIP device visible */
+} tf_status;
+
+/* --- twofold functions, binary64 --------------------------------------- */
+/* texp: z0 = exp(x0) (1x), z1 ~ e^(x0+x1) - z0.  Section "Exponent:
+ * Algorithm summary", algorithm texp(x0 + x1): v = pexp0(x0) (table E (C T)
+ * with a degree-12 Taylor-Horner T in twofold arithmetic), t1 = expm1(x1),
+ * z1 = z0 t1 + (v1 + (v0 - z0)). */
+tf_status tf_texp(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                  void* stream);
+/* texpm1: z0 = expm1(x0), z1 ~ (e^(x0+x1) - 1) - z0; w = pexpm10(x0),
+ * z1 = (z0 + 1) t1 + (w1 + (w0 - z0)).  Same section, algorithm texpm1. */
+tf_status tf_texpm1(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                    void* stream);
+/* tlog: z0 = log(x0), z1 ~ log(x0 + x1) - z0 by one Newton step on pexpm10
+ * seeded with a 1x log1p (section "Logarithm: Algorithm summary", tlog/plog). */
+tf_status tf_tlog(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                  void* stream);
+/* tlog1p: z0 = log1p(x0), z1 ~ log1p(x0 + x1) - z0 (tlog1p/plog1p). */
+tf_status tf_tlog1p(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                    void* stream);
+
+/* --- twofold functions, binary32 (same algorithms, float parameters:
+ *     pexp0 L = 1, N = 6; pexpm10 N = 5) ---------------------------------- */
+tf_status tf_texpf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                   void* stream);
+tf_status tf_texpm1f(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                     void* stream);
+tf_status tf_tlogf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                   void* stream);
+tf_status tf_tlog1pf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                     void* stream);
+
+/* --- the 1x functions that define the main parts z0 --------------------
+ * z[i] = f(x[i]); the same values the twofold functions return as z0. */
+tf_status tf_exp1x(const double* x, double* z, size_t n, void* stream);
+tf_status tf_expm1_1x(const double* x, double* z, size_t n, void* stream);
+tf_status tf_log1x(const double* x, double* z, size_t n, void* stream);
+tf_status tf_log1p_1x(const double* x, double* z, size_t n, void* stream);
+tf_status tf_exp1xf(const float* x, float* z, size_t n, void* stream);
+tf_status tf_expm1_1xf(const float* x, float* z, size_t n, void* stream);
+tf_status tf_log1xf(const float* x, float* z, size_t n, void* stream);
+tf_status tf_log1p_1xf(const float* x, float* z, size_t n, void* stream);
+
+/* --- library information ---------------------------------------------- */
+const char* tf_status_string(tf_status s);
+const char* tf_version(void);
+int tf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TWOFOLD_HIP_H */

@@ -1,0 +1,58 @@
+"""MI355X-native twofold exp/log (E. Latkin, "Twofold exp and log", 2015).
+
+Elementwise twofold functions over split arrays of twofolds x0 + x1 on the
+GPU, in binary64 and binary32:
+
+    z0, z1 = texp(x0, x1)      # z0 = exp(x0) bitwise, z0 + z1 ~ e^(x0 + x1)
+    z0, z1 = texpm1(x0, x1)    # expm1
+    z0, z1 = tlog(x0, x1)      # log
+    z0, z1 = tlog1p(x0, x1)    # log1p
+    z = exp1x(x), expm1_1x(x), log1x(x), log1p_1x(x)   # the 1x main parts
+
+Arguments are contiguous torch tensors on the GPU; work is enqueued on the
+current stream.  The kernels live in libtwofold_hip.so (csrc/, C ABI in
+include/twofold_hip.h); this package only marshals arguments.
+"""
+from ._lib import (ONEX, TWOFOLD, TwofoldError, declared_functions, lib, onex_call,
+                   twofold_call)
+
+
+def texp(x0, x1, out=None):
+    return twofold_call("texp", x0, x1, out)
+
+
+def texpm1(x0, x1, out=None):
+    return twofold_call("texpm1", x0, x1, out)
+
+
+def tlog(x0, x1, out=None):
+    return twofold_call("tlog", x0, x1, out)
+
+
+def tlog1p(x0, x1, out=None):
+    return twofold_call("tlog1p", x0, x1, out)
+
+
+def exp1x(x, out=None):
+    return onex_call("exp1x", x, out)
+
+
+def expm1_1x(x, out=None):
+    return onex_call("expm1_1x", x, out)
+
+
+def log1x(x, out=None):
+    return onex_call("log1x", x, out)
+
+
+def log1p_1x(x, out=None):
+    return onex_call("log1p_1x", x, out)
+
+
+def build(verbose=False):
+    from . import _build
+    return _build.build(verbose=verbose)
+
+
+__all__ = ["texp", "texpm1", "tlog", "tlog1p", "exp1x", "expm1_1x", "log1x", "log1p_1x",
+           "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX"]

@@ -1,0 +1,130 @@
+"""ctypes binding of libtwofold_hip.so (include/twofold_hip.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels.  Tensors must be contiguous CUDA (HIP) tensors of one dtype
+(float64 -> tf_<fn>, float32 -> tf_<fn>f); calls are enqueued on
+torch.cuda.current_stream().  There is no CPU fallback: without the built
+library or a GPU the functions raise.
+"""
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libtwofold_hip.so")
+HEADER = os.path.join(ROOT, "include", "twofold_hip.h")
+
+TF_OK, TF_EINVAL, TF_ELAUNCH, TF_ENOMEM, TF_EUNSUPPORTED, TF_ENODEV = range(6)
+
+TWOFOLD = ("texp", "texpm1", "tlog", "tlog1p")
+ONEX = ("exp1x", "expm1_1x", "log1x", "log1p_1x")
+
+_lib = None
+
+
+class TwofoldError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        msg = _load().tf_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__("%s: %s (status %d)" % (what, msg, status))
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libtwofold_hip.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, S = ctypes.c_void_p, ctypes.c_size_t
+    for f in TWOFOLD:
+        for sfx in ("", "f"):
+            fn = getattr(lib, "tf_" + f + sfx)
+            fn.argtypes = [P, P, P, P, S, P]
+            fn.restype = ctypes.c_int
+    for f in ONEX:
+        for sfx in ("", "f"):
+            fn = getattr(lib, "tf_" + f + sfx)
+            fn.argtypes = [P, P, S, P]
+            fn.restype = ctypes.c_int
+    lib.tf_status_string.argtypes = [ctypes.c_int]
+    lib.tf_status_string.restype = ctypes.c_char_p
+    lib.tf_version.restype = ctypes.c_char_p
+    lib.tf_abi_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def lib():
+    """The ctypes handle (loads the in-tree library)."""
+    return _load()
+
+
+def declared_functions():
+    """Names of the functions include/twofold_hip.h declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tf_\w+)\s*\(", src)))
+
+
+def _check(status, what):
+    if status != TF_OK:
+        raise TwofoldError(status, what)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _suffix(t):
+    import torch
+    if t.dtype == torch.float64:
+        return ""
+    if t.dtype == torch.float32:
+        return "f"
+    raise TypeError("twofold arrays must be float64 or float32, got %s" % t.dtype)
+
+
+def _validate(*ts):
+    t0 = ts[0]
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("twofold arrays must be GPU tensors")
+        if t.dtype != t0.dtype or t.shape != t0.shape or t.device != t0.device:
+            raise ValueError("twofold arrays must share dtype, shape and device")
+        if not t.is_contiguous():
+            raise ValueError("twofold arrays must be contiguous")
+
+
+def twofold_call(name, x0, x1, out=None):
+    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD."""
+    import torch
+    if name not in TWOFOLD:
+        raise ValueError(name)
+    _validate(x0, x1)
+    if out is None:
+        z0 = torch.empty_like(x0)
+        z1 = torch.empty_like(x0)
+    else:
+        z0, z1 = out
+        _validate(x0, z0, z1)
+    fn = getattr(_load(), "tf_" + name + _suffix(x0))
+    with torch.cuda.device(x0.device):
+        _check(fn(x0.data_ptr(), x1.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(),
+                  _stream()), "tf_" + name)
+    return z0, z1
+
+
+def onex_call(name, x, out=None):
+    import torch
+    if name not in ONEX:
+        raise ValueError(name)
+    _validate(x)
+    z = torch.empty_like(x) if out is None else out
+    _validate(x, z)
+    fn = getattr(_load(), "tf_" + name + _suffix(x))
+    with torch.cuda.device(x.device):
+        _check(fn(x.data_ptr(), z.data_ptr(), x.numel(), _stream()), "tf_" + name)
+    return z

@@ -1,0 +1,487 @@
+// Device-side twofold arithmetic, 1x functions and twofold exp/log cores for
+// gfx950 (binary64 and binary32).  Every function here is inlined into the
+// kernels of tf_kernels.hip; tables are read from LDS through the pointers
+// the kernels pass in.
+//
+// Bit-reproducibility: the library is compiled with -ffp-contract=off, so the
+// compiler never fuses a*b+c; every fused multiply-add is an explicit ffma().
+// Every step is one IEEE operation (+ - * fma, rint, ldexp, frexp) or integer
+// bit manipulation, so a given sequence gives the same bits on any IEEE
+// machine.  Branches of the method become selects; index arithmetic is done on
+// clamped arguments so that a table read can never leave its table, whatever
+// the input (NaN, infinities).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tf_tables.inc"
+
+namespace tfh {
+
+template <class T> struct Tw { T x0, x1; };
+
+// ----------------------------------------------------------------------------
+// IEEE primitives
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double frint(double a) { return __builtin_rint(a); }
+__device__ __forceinline__ float frint(float a) { return __builtin_rintf(a); }
+__device__ __forceinline__ double fldexp(double a, int k) { return __builtin_amdgcn_ldexp(a, k); }
+__device__ __forceinline__ float fldexp(float a, int k) { return __builtin_amdgcn_ldexpf(a, k); }
+__device__ __forceinline__ double fabs_(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float fabs_(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double frexp_mant(double a) { return __builtin_amdgcn_frexp_mant(a); }
+__device__ __forceinline__ float frexp_mant(float a) { return __builtin_amdgcn_frexp_mantf(a); }
+__device__ __forceinline__ int frexp_exp(double a) { return __builtin_amdgcn_frexp_exp(a); }
+__device__ __forceinline__ int frexp_exp(float a) { return __builtin_amdgcn_frexp_expf(a); }
+__device__ __forceinline__ bool isnan_(double a) { return __builtin_isnan(a); }
+__device__ __forceinline__ bool isnan_(float a) { return __builtin_isnan(a); }
+
+// ----------------------------------------------------------------------------
+// Format parameters
+// ----------------------------------------------------------------------------
+constexpr double fact_ratio(int n, int j) {  // n!/j!, exact for n <= 12
+    double r = 1.0;
+    for (int i = j + 1; i <= n; ++i) r *= i;
+    return r;
+}
+
+template <class T> struct P;
+
+template <> struct P<double> {
+    using V2 = double2;
+    using U = uint64_t;
+    static constexpr int L = TFH_D_L, K = TFH_D_K, N = TFH_D_N, N1 = TFH_D_N1;
+    static constexpr int E_OFF = TFH_D_E_OFF, E_CNT = TFH_D_E_CNT;
+    static constexpr int C_OFF = TFH_D_C_OFF, C_CNT = TFH_D_C_CNT;
+    static constexpr int CM1_OFF = TFH_D_CM1_OFF, CM1_CNT = TFH_D_CM1_CNT;
+    static constexpr int MANT = 52, EXPMASK = 0x7ff, BIAS = 1023, SUBSCALE = 54;
+    static constexpr U MANT_MASK = 0x000fffffffffffffull;
+    static constexpr U ONE_BITS = 0x3ff0000000000000ull;   // exponent field of [1,2)
+    static constexpr U HALF_BITS = 0x3fe0000000000000ull;  // exponent field of [1/2,1)
+    static constexpr double MIN_NORMAL = 0x1p-1022;
+    static constexpr double INF = __builtin_inf();
+    static constexpr double LN2_HI = TFH_D_LN2_HI, LN2_LO = TFH_D_LN2_LO;
+    static constexpr double RCP_HI = TFH_D_RCP_HI, RCP_LO = TFH_D_RCP_LO;
+    static constexpr double INV_L = TFH_D_INV_L, L1 = TFH_D_L1, L2 = TFH_D_L2;
+    static constexpr double LN2X_HI = TFH_D_LN2X_HI, LN2X_LO = TFH_D_LN2X_LO;
+    static constexpr double EXP_XMAX = TFH_D_EXP_XMAX, EXPM1_XMAX = TFH_D_EXPM1_XMAX;
+    static constexpr double EXP_XLO = TFH_D_EXP_XLO, EXPM1_XNEG = TFH_D_EXPM1_XNEG;
+    static constexpr double EXPM1_TINY = TFH_D_EXPM1_TINY, LOG1P_TINY = TFH_D_LOG1P_TINY;
+    static constexpr int EXP_NC = TFH_D_EXP_NC, LOG_NC = TFH_D_LOG_NC;
+    static constexpr double EXP_C[EXP_NC] = {TFH_D_EXP_C_LIST};
+    static constexpr double LOG_C[LOG_NC] = {TFH_D_LOG_C_LIST};
+    __device__ static U bits(double x) { return (U)__double_as_longlong(x); }
+    __device__ static double from_bits(U b) { return __longlong_as_double((long long)b); }
+    __device__ static double qnan() { return __builtin_nan(""); }
+};
+
+template <> struct P<float> {
+    using V2 = float2;
+    using U = uint32_t;
+    static constexpr int L = TFH_F_L, K = TFH_F_K, N = TFH_F_N, N1 = TFH_F_N1;
+    static constexpr int E_OFF = TFH_F_E_OFF, E_CNT = TFH_F_E_CNT;
+    static constexpr int C_OFF = TFH_F_C_OFF, C_CNT = TFH_F_C_CNT;
+    static constexpr int CM1_OFF = TFH_F_CM1_OFF, CM1_CNT = TFH_F_CM1_CNT;
+    static constexpr int MANT = 23, EXPMASK = 0xff, BIAS = 127, SUBSCALE = 25;
+    static constexpr U MANT_MASK = 0x007fffffu;
+    static constexpr U ONE_BITS = 0x3f800000u;
+    static constexpr U HALF_BITS = 0x3f000000u;
+    static constexpr float MIN_NORMAL = 0x1p-126f;
+    static constexpr float INF = __builtin_inff();
+    static constexpr float LN2_HI = TFH_F_LN2_HI, LN2_LO = TFH_F_LN2_LO;
+    static constexpr float RCP_HI = TFH_F_RCP_HI, RCP_LO = TFH_F_RCP_LO;
+    static constexpr float INV_L = TFH_F_INV_L, L1 = TFH_F_L1, L2 = TFH_F_L2;
+    static constexpr float LN2X_HI = TFH_F_LN2X_HI, LN2X_LO = TFH_F_LN2X_LO;
+    static constexpr float EXP_XMAX = TFH_F_EXP_XMAX, EXPM1_XMAX = TFH_F_EXPM1_XMAX;
+    static constexpr float EXP_XLO = TFH_F_EXP_XLO, EXPM1_XNEG = TFH_F_EXPM1_XNEG;
+    static constexpr float EXPM1_TINY = TFH_F_EXPM1_TINY, LOG1P_TINY = TFH_F_LOG1P_TINY;
+    static constexpr int EXP_NC = TFH_F_EXP_NC, LOG_NC = TFH_F_LOG_NC;
+    static constexpr float EXP_C[EXP_NC] = {TFH_F_EXP_C_LIST};
+    static constexpr float LOG_C[LOG_NC] = {TFH_F_LOG_C_LIST};
+    __device__ static U bits(float x) { return (U)__float_as_uint(x); }
+    __device__ static float from_bits(U b) { return __uint_as_float(b); }
+    __device__ static float qnan() { return __builtin_nanf(""); }
+};
+
+// ----------------------------------------------------------------------------
+// Twofold arithmetic (error-free transforms with the FMA exact product).
+// Outputs of fast_two_sum / two_sum / two_prod are the unique exact rounding
+// errors, so the fast form is used wherever |a| >= |b| (or a = 0) is proven.
+// ----------------------------------------------------------------------------
+template <class T> __device__ __forceinline__ Tw<T> fast_two_sum(T a, T b) {
+    T s = a + b;
+    T t = b - (s - a);
+    return {s, t};
+}
+template <class T> __device__ __forceinline__ Tw<T> two_sum(T a, T b) {
+    T s = a + b;
+    T bp = s - a;
+    T ap = s - bp;
+    T db = b - bp;
+    T da = a - ap;
+    return {s, da + db};
+}
+template <class T> __device__ __forceinline__ Tw<T> two_prod(T a, T b) {
+    T p = a * b;
+    return {p, ffma(a, b, -p)};
+}
+template <class T> __device__ __forceinline__ Tw<T> mul_td(Tw<T> A, T c) {
+    Tw<T> pe = two_prod(A.x0, c);
+    return {pe.x0, ffma(A.x1, c, pe.x1)};
+}
+template <class T> __device__ __forceinline__ Tw<T> add_td_fast(Tw<T> A, T c) {
+    Tw<T> st = fast_two_sum(c, A.x0);
+    return {st.x0, st.x1 + A.x1};
+}
+template <class T> __device__ __forceinline__ Tw<T> add_td(Tw<T> A, T c) {
+    Tw<T> st = two_sum(A.x0, c);
+    return {st.x0, st.x1 + A.x1};
+}
+template <class T> __device__ __forceinline__ Tw<T> mul_tt(Tw<T> A, Tw<T> B) {
+    Tw<T> pe = two_prod(A.x0, B.x0);
+    return {pe.x0, ffma(A.x0, B.x1, ffma(A.x1, B.x0, pe.x1))};
+}
+template <class T> __device__ __forceinline__ Tw<T> add_tt(Tw<T> A, Tw<T> B) {
+    Tw<T> st = two_sum(A.x0, B.x0);
+    return {st.x0, st.x1 + (A.x1 + B.x1)};
+}
+template <class T> __device__ __forceinline__ Tw<T> add_tt_fast(Tw<T> A, Tw<T> B) {
+    Tw<T> st = fast_two_sum(A.x0, B.x0);
+    return {st.x0, st.x1 + (A.x1 + B.x1)};
+}
+template <class T> __device__ __forceinline__ Tw<T> div_tt(Tw<T> A, Tw<T> B) {
+    T q0 = A.x0 / B.x0;
+    T r = ffma(-q0, B.x0, A.x0);
+    T q1 = ((r + A.x1) - q0 * B.x1) / B.x0;
+    return {q0, q1};
+}
+template <class T> __device__ __forceinline__ Tw<T> sel(bool c, Tw<T> a, Tw<T> b) {
+    return {c ? a.x0 : b.x0, c ? a.x1 : b.x1};
+}
+
+// ----------------------------------------------------------------------------
+// LDS table views
+// ----------------------------------------------------------------------------
+template <class T> struct ExpTab {        // 2^(j/32) twofolds for the 1x exp/expm1
+    const typename P<T>::V2* S;
+};
+template <class T> struct LogTab {        // 1x log cells
+    const T* INVC;
+    const typename P<T>::V2* LOG;
+};
+template <class T> struct Pexp0Tab {      // pexp0: E = Ehat 2^k and C = e^(n/32)/N!
+    const typename P<T>::V2* E;
+    const int* EK;
+    const typename P<T>::V2* C;
+};
+template <class T> struct Pm1Tab {        // pexpm10: e^(n/128) - 1
+    const typename P<T>::V2* CM1;
+};
+
+// ----------------------------------------------------------------------------
+// 1x functions (main parts z0)
+// ----------------------------------------------------------------------------
+template <class T> __device__ __forceinline__ T exp_q(T r) {
+    T q = P<T>::EXP_C[P<T>::EXP_NC - 1];
+#pragma unroll
+    for (int i = P<T>::EXP_NC - 2; i >= 0; --i) q = ffma(r, q, P<T>::EXP_C[i]);
+    return q;
+}
+template <class T> __device__ __forceinline__ T log_q(T r) {
+    T q = P<T>::LOG_C[P<T>::LOG_NC - 1];
+#pragma unroll
+    for (int i = P<T>::LOG_NC - 2; i >= 0; --i) q = ffma(r, q, P<T>::LOG_C[i]);
+    return q;
+}
+
+// exp(x): x = (32m + j) ln2/32 + r, e^x = 2^m 2^(j/32) e^r.
+template <class T> __device__ __forceinline__ T exp1x(T x, ExpTab<T> t) {
+    using K = P<T>;
+    T xc = (x >= K::EXP_XLO) ? x : K::EXP_XLO;
+    xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
+    T kd = frint(xc * K::INV_L);
+    int k = (int)kd;
+    T r = ffma(-kd, K::L1, xc);
+    r = ffma(-kd, K::L2, r);
+    T p = ffma(r * r, exp_q(r), r);
+    int j = k & 31, m = (k - j) >> 5;
+    typename K::V2 s = t.S[j];
+    T y = s.x + ffma(s.x, p, s.y);
+    T res = fldexp(y, m);
+    res = (x < K::EXP_XLO) ? T(0) : res;
+    res = (x > K::EXP_XMAX) ? K::INF : res;
+    return isnan_(x) ? x + x : res;
+}
+
+// expm1 for |x| < EXPM1_TINY: x + x^2/2 (zero keeps its sign).
+template <class T> __device__ __forceinline__ T expm1_tiny(T x) {
+    return (x == T(0)) ? x : ffma(x, x * T(0.5), x);
+}
+
+// expm1(x): the reduction of exp with r = rhi + rlo; the -1 enters as -2^-m in
+// the scaled domain through exact transforms.
+template <class T> __device__ __forceinline__ T expm1_1x(T x, ExpTab<T> t) {
+    using K = P<T>;
+    T xc = (x >= K::EXPM1_XNEG) ? x : K::EXPM1_XNEG;
+    xc = (xc <= K::EXPM1_XMAX) ? xc : K::EXPM1_XMAX;
+    T kd = frint(xc * K::INV_L);
+    int k = (int)kd;
+    T rhi = ffma(-kd, K::L1, xc);
+    T rlo = -kd * K::L2;
+    T r = rhi + rlo;
+    T plo = ffma(r * r, exp_q(r), rlo);
+    int j = k & 31, m = (k - j) >> 5;
+    typename K::V2 s = t.S[j];
+    Tw<T> A = two_sum(s.x, -fldexp(T(1), -m));
+    Tw<T> B = two_prod(s.x, rhi);
+    T c = ffma(s.x, plo, ffma(s.y, rhi, s.y));
+    Tw<T> H = two_sum(A.x0, B.x0);
+    T tail = H.x1 + ((A.x1 + B.x1) + c);
+    T res = fldexp(H.x0 + tail, m);
+    res = (fabs_(x) < K::EXPM1_TINY) ? expm1_tiny(x) : res;
+    res = (x < K::EXPM1_XNEG) ? T(-1) : res;
+    res = (x > K::EXPM1_XMAX) ? K::INF : res;
+    return isnan_(x) ? x + x : res;
+}
+
+// u = z 2^e with z in [3/4, 3/2), cell i = top 7 significand bits (u > 0 normal).
+template <class T> struct LogSplit { T z; int e; int i; };
+template <class T> __device__ __forceinline__ LogSplit<T> log_split(T u) {
+    using K = P<T>;
+    typename K::U b = K::bits(u);
+    int e = (int)((b >> K::MANT) & K::EXPMASK) - K::BIAS;
+    int i = (int)((b >> (K::MANT - 7)) & 127);
+    bool hi = i >= 64;
+    typename K::U zb = (b & K::MANT_MASK) | (hi ? K::HALF_BITS : K::ONE_BITS);
+    return {K::from_bits(zb), e + (hi ? 1 : 0), i};
+}
+
+// log(x) = e ln2 - log(invc) + log1p(z invc - 1), z invc - 1 exact.
+template <class T> __device__ __forceinline__ T log1x(T x, LogTab<T> t) {
+    using K = P<T>;
+    bool sub = x < K::MIN_NORMAL;
+    T xs = sub ? fldexp(x, K::SUBSCALE) : x;
+    LogSplit<T> ls = log_split(xs);
+    int e = ls.e - (sub ? K::SUBSCALE : 0);
+    T r = ffma(ls.z, t.INVC[ls.i], T(-1));
+    T ed = (T)e;
+    typename K::V2 lg = t.LOG[ls.i];
+    T hi = ffma(ed, K::LN2X_HI, lg.x);
+    T lo = ffma(ed, K::LN2X_LO, lg.y);
+    T tail = ffma(r * r, log_q(r), lo);
+    Tw<T> st = fast_two_sum(hi, r);
+    T res = st.x0 + (st.x1 + tail);
+    res = (x == K::INF) ? K::INF : res;
+    res = (x == T(0)) ? -K::INF : res;
+    res = (x < T(0)) ? K::qnan() : res;
+    return isnan_(x) ? x + x : res;
+}
+
+// log1p(x): u + c = 1 + x exactly, log(u) with c folded into r; |x| < 2^-8
+// uses r = x directly.
+template <class T> __device__ __forceinline__ T log1p_1x(T x, LogTab<T> t) {
+    using K = P<T>;
+    Tw<T> u = two_sum(T(1), x);
+    LogSplit<T> ls = log_split(u.x0);
+    T invc = t.INVC[ls.i];
+    T rhi = ffma(ls.z, invc, T(-1));
+    T rlo = fldexp(u.x1, -ls.e) * invc;
+    bool small = fabs_(x) < T(0.00390625);
+    rhi = small ? x : rhi;
+    rlo = small ? T(0) : rlo;
+    T ed = (T)ls.e;
+    typename K::V2 lg = t.LOG[ls.i];
+    T hi = ffma(ed, K::LN2X_HI, lg.x);
+    T lo = ffma(ed, K::LN2X_LO, lg.y);
+    T tail = ffma(rhi * rhi, log_q(rhi), lo + ffma(-rlo, rhi, rlo));
+    Tw<T> st = fast_two_sum(hi, rhi);
+    T res = st.x0 + (st.x1 + tail);
+    res = (fabs_(x) < K::LOG1P_TINY) ? x : res;
+    res = (x == K::INF) ? K::INF : res;
+    res = (x == T(-1)) ? -K::INF : res;
+    res = (x < T(-1)) ? K::qnan() : res;
+    return isnan_(x) ? x + x : res;
+}
+
+// ----------------------------------------------------------------------------
+// pexp0 core: x in [EXP_XLO, EXP_XMAX].  x = 2^L m + n/32 + y exactly;
+// T = e^y N! by twofold Horner; V = Ehat (C T), e^x ~ (V0 + V1) 2^k.
+// ----------------------------------------------------------------------------
+template <class T> struct Scaled { Tw<T> v; int k; };
+
+template <class T> __device__ __forceinline__ Tw<T> horner_exp(T y) {
+    constexpr int N = P<T>::N;
+    Tw<T> p = fast_two_sum(T(N), y);
+#pragma unroll
+    for (int j = N - 2; j >= 0; --j) p = add_td_fast(mul_td(p, y), T(fact_ratio(N, j)));
+    return p;
+}
+
+template <class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab<T> t) {
+    using K = P<T>;
+    constexpr int SH = K::L + K::K;
+    T Md = frint(x * T(1 << K::K));
+    T y = ffma(-Md, T(1.0 / (1 << K::K)), x);          // exact: x - M 2^-K
+    int M = (int)Md;
+    int a = M < 0 ? -M : M;
+    int m = a >> SH, n = a & ((1 << SH) - 1);
+    m = M < 0 ? -m : m;
+    n = M < 0 ? -n : n;
+    // callers pass x in [EXP_XLO, EXP_XMAX], where these clamps do nothing
+    m = m < -K::E_OFF ? -K::E_OFF : (m > K::E_CNT - 1 - K::E_OFF ? K::E_CNT - 1 - K::E_OFF : m);
+    n = n < -K::C_OFF ? -K::C_OFF : (n > K::C_OFF ? K::C_OFF : n);
+    Tw<T> Tt = horner_exp(y);
+    typename K::V2 e2 = t.E[m + K::E_OFF];
+    typename K::V2 c2 = t.C[n + K::C_OFF];
+    int k = t.EK[m + K::E_OFF];
+    Tw<T> V = mul_tt(Tw<T>{e2.x, e2.y}, mul_tt(Tw<T>{c2.x, c2.y}, Tt));
+    return {V, k};
+}
+
+// pexpm10 small path, |x| <= 89.5/128: x = n/128 + y, T = (e^y - 1) via the
+// Horner of N1 without its last term, times y and the twofold 1/N1!,
+// Z = (C + T) + C T with C = e^(n/128) - 1.
+template <class T> __device__ __forceinline__ Tw<T> pexpm10_small(T x, Pm1Tab<T> t) {
+    using K = P<T>;
+    constexpr int N1 = K::N1;
+    // Valid arguments satisfy |x| <= ln 2 + tiny < 89/128; anything else (NaN,
+    // inf from an invalid lane) is replaced so the index stays in [-89, 89].
+    T xs = (fabs_(x) <= T(0.6953125)) ? x : T(0);
+    T nd = frint(xs * T(128));
+    T y = ffma(-nd, T(1.0 / 128), xs);                  // exact
+    int n = (int)nd;
+    n = n < -K::CM1_OFF ? -K::CM1_OFF : (n > K::CM1_OFF ? K::CM1_OFF : n);
+    Tw<T> p = fast_two_sum(T(N1), y);
+#pragma unroll
+    for (int j = N1 - 2; j >= 1; --j) p = add_td_fast(mul_td(p, y), T(fact_ratio(N1, j)));
+    p = mul_td(p, y);
+    Tw<T> Tt = mul_tt(p, Tw<T>{K::RCP_HI, K::RCP_LO});
+    typename K::V2 c2 = t.CM1[n + K::CM1_OFF];
+    Tw<T> C = {c2.x, c2.y};
+    return add_tt_fast(add_tt_fast(C, Tt), mul_tt(C, Tt));
+}
+
+// The rule for non-finite main parts: z0 NaN -> z1 NaN, z0 = +-inf -> z1 = +0.
+template <class T> __device__ __forceinline__ T special_rule(T z0, T z1) {
+    z1 = (fabs_(z0) == P<T>::INF) ? T(0) : z1;
+    return isnan_(z0) ? P<T>::qnan() : z1;
+}
+
+// ----------------------------------------------------------------------------
+// Twofold functions, one element each.  `x1_tiny` is a wave-uniform flag: all
+// active lanes have |x1| < EXPM1_TINY, so expm1(x1) is its tiny branch.
+// ----------------------------------------------------------------------------
+template <class T> __device__ __forceinline__ T expm1_of_x1(T x1, bool x1_tiny, ExpTab<T> et) {
+    return x1_tiny ? expm1_tiny(x1) : expm1_1x(x1, et);
+}
+
+template <class T>
+__device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et, Pexp0Tab<T> pt,
+                                          T& z0o, T& z1o) {
+    using K = P<T>;
+    T z0 = exp1x(x0, et);
+    T t1 = expm1_of_x1(x1, x1_tiny, et);
+    bool in = x0 >= K::EXP_XLO;                       // below: pexp0 gives (0, 0)
+    T xc = in ? x0 : K::EXP_XLO;
+    xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
+    Scaled<T> s = pexp0_core(xc, pt);
+    T v0 = in ? s.v.x0 : T(0);
+    T v1 = in ? s.v.x1 : T(0);
+    int k = in ? s.k : 0;
+    T z0s = fldexp(z0, -k);                           // exact
+    T z1s = z0s * t1 + (v1 + (v0 - z0s));
+    z0o = z0;
+    z1o = special_rule(z0, fldexp(z1s, k));
+}
+
+template <class T>
+__device__ __forceinline__ void texpm1_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et, Pexp0Tab<T> pt,
+                                            Pm1Tab<T> mt, T& z0o, T& z1o) {
+    using K = P<T>;
+    T z0 = expm1_1x(x0, et);
+    T t1 = expm1_of_x1(x1, x1_tiny, et);
+    bool small = fabs_(x0) <= K::LN2_HI;
+    Tw<T> w = pexpm10_small(small ? x0 : T(0), mt);
+    bool big = !small && x0 >= K::EXP_XLO && x0 <= K::EXP_XMAX;
+    if (__any(big)) {                                 // pexp0(x0) - 1 on this wave
+        T xc = big ? x0 : T(1);
+        Scaled<T> s = pexp0_core(xc, pt);
+        Tw<T> wl = add_td(Tw<T>{fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k)}, T(-1));
+        w = big ? wl : w;
+    }
+    w = (x0 < K::EXP_XLO) ? Tw<T>{T(-1), T(0)} : w;  // pexp0 = (0, 0) below range
+    T z1 = (z0 + T(1)) * t1 + (w.x1 + (w.x0 - z0));
+    z0o = z0;
+    z1o = special_rule(z0, z1);
+}
+
+// Newton step shared by plog and plog1p: r0 = log1p(a0 + a1), s = pexpm10(-r0),
+// u = ((a s) + a) + s, r1 = u0 + u1.
+template <class T>
+__device__ __forceinline__ Tw<T> plog_newton(Tw<T> a, LogTab<T> lt, Pm1Tab<T> mt) {
+    T r0 = log1p_1x(a.x0 + a.x1, lt);
+    Tw<T> s = pexpm10_small(-r0, mt);
+    Tw<T> u = add_tt(add_tt(mul_tt(a, s), a), s);
+    return {r0, u.x0 + u.x1};
+}
+
+template <class T> __device__ __forceinline__ Tw<T> add_n_ln2(Tw<T> X, int n) {
+    return add_tt(X, mul_td(Tw<T>{P<T>::LN2_HI, P<T>::LN2_LO}, (T)n));
+}
+
+// w = 2^n z: frexp when w0 < 1/2 or w0 > 2, else n = 0.
+template <class T> __device__ __forceinline__ Tw<T> log_scale(Tw<T> w, int& n) {
+    bool need = w.x0 < T(0.5) || w.x0 > T(2);
+    int ne = frexp_exp(w.x0);
+    Tw<T> z = {frexp_mant(w.x0), fldexp(w.x1, -ne)};
+    n = need ? ne : 0;
+    return sel(need, z, w);
+}
+
+// x1 of a log whose renormalised argument w0 is outside (0, inf).
+template <class T> __device__ __forceinline__ T log_domain_x1(T w0, T x1) {
+    x1 = (w0 == P<T>::INF) ? P<T>::INF : x1;
+    x1 = (w0 == T(0)) ? -P<T>::INF : x1;
+    return (w0 < T(0) || isnan_(w0)) ? P<T>::qnan() : x1;
+}
+
+template <class T>
+__device__ __forceinline__ void tlog_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o, T& x1o) {
+    T x0 = log1x(y0, lt);
+    Tw<T> v = two_sum(y0, y1);
+    int n;
+    Tw<T> z = log_scale(v, n);
+    Tw<T> a = {z.x0 - T(1), z.x1};                    // exact
+    Tw<T> X = add_n_ln2(plog_newton(a, lt, mt), n);
+    T x1 = X.x1 + (X.x0 - x0);
+    x1 = log_domain_x1(v.x0, x1);
+    x0o = x0;
+    x1o = special_rule(x0, x1);
+}
+
+template <class T>
+__device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o,
+                                            T& x1o) {
+    using K = P<T>;
+    T x0 = log1p_1x(y0, lt);
+    Tw<T> v = two_sum(y0, y1);
+    bool outer = v.x0 < T(-0.5) || v.x0 > T(1);
+    Tw<T> w = add_td(v, T(1));
+    w = two_sum(w.x0, w.x1);                          // renormalised 1 + y
+    int nn;
+    Tw<T> z = log_scale(w, nn);
+    Tw<T> a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
+    Tw<T> R = plog_newton(a, lt, mt);
+    Tw<T> X = sel(outer, add_n_ln2(R, outer ? nn : 0), R);
+    T x1 = X.x1 + (X.x0 - x0);
+    x1 = outer ? log_domain_x1(w.x0, x1) : x1;
+    x1 = (v.x0 == K::INF) ? K::INF : x1;
+    x1 = isnan_(v.x0) ? K::qnan() : x1;
+    x0o = x0;
+    x1o = special_rule(x0, x1);
+}
+
+}  // namespace tfh

@@ -1,0 +1,103 @@
+"""The C ABI library (no GPU needed): it loads, exports every function that
+include/twofold_hip.h declares, and validates arguments before any HIP call
+(n == 0 -> TF_OK, NULL array with n > 0 -> TF_EINVAL).  Also: the GPU
+library's tables equal the oracle's, value for value -- two generators written
+independently (decimal vs mpmath) from the same definitions."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tables_util import parse_header
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1502_05216_amd", "libtwofold_hip.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1502_05216_amd import _build
+        _build.build()
+    from paper_1502_05216_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1502_05216_amd import declared_functions
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version(lib):
+    for s in range(6):
+        assert lib.tf_status_string(s)
+    assert b"gfx950" in lib.tf_version()
+    assert lib.tf_abi_version() == 1
+
+
+@pytest.mark.parametrize("name", ["tf_texp", "tf_texpm1", "tf_tlog", "tf_tlog1p",
+                                  "tf_texpf", "tf_texpm1f", "tf_tlogf", "tf_tlog1pf"])
+def test_twofold_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    # n == 0: nothing to do, no HIP call
+    assert fn(None, None, None, None, 0, None) == 0
+    # a NULL array with n > 0 is rejected before any HIP call
+    fake = ctypes.c_void_p(0x1000)
+    for k in range(4):
+        args = [fake] * 4
+        args[k] = None
+        assert fn(*args, 10, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tf_exp1x", "tf_expm1_1x", "tf_log1x", "tf_log1p_1x",
+                                  "tf_exp1xf", "tf_expm1_1xf", "tf_log1xf", "tf_log1p_1xf"])
+def test_onex_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, 0, None) == 0
+    assert fn(None, ctypes.c_void_p(0x1000), 5, None) == 1
+    assert fn(ctypes.c_void_p(0x1000), None, 5, None) == 1
+
+
+def _hip_tables():
+    src = open(os.path.join(ROOT, "paper_1502_05216_amd", "csrc", "tf_tables.inc")).read()
+    out = {}
+    for name, body in re.findall(r"__device__ const \w+ (\w+)\[\d+\] = \{(.*?)\};", src, re.S):
+        toks = [t for t in re.split(r"[,{}\s]+", body) if t]
+        out[name] = [float.fromhex(t.rstrip("f")) if "0x" in t or "." in t else int(t)
+                     for t in toks]
+    for name, val in re.findall(r"#define (TFH_\w+) (\S+)$", src, re.M):
+        if "LIST" in name:
+            continue
+        out[name] = float.fromhex(val.rstrip("f")) if "0x" in val or "." in val else int(val)
+    for name, val in re.findall(r"#define (TFH_\w+_LIST) (.+)$", src, re.M):
+        out[name] = [float.fromhex(v.strip().rstrip("f")) for v in val.split(",")]
+    return out
+
+
+@pytest.mark.parametrize("f", ["D", "F"])
+def test_gpu_tables_equal_oracle_tables(f):
+    H = _hip_tables()
+    O = parse_header(os.path.join(ROOT, "oracle", "tfo_tables.h"))
+    o = lambda k: O["TFO_%s_%s" % (f, k)]
+    h = lambda k: H["TFH_%s_%s" % (f, k)]
+
+    def inter(hi, lo):
+        return [v for pair in zip(hi, lo) for v in pair]
+
+    assert h("E") == inter(o("E_HI"), o("E_LO"))
+    assert h("EK") == o("E_K")
+    assert h("C") == inter(o("C_HI"), o("C_LO"))
+    assert h("CM1") == inter(o("CM1_HI"), o("CM1_LO"))
+    assert h("S") == inter(o("S_HI"), o("S_LO"))
+    assert h("LOG") == inter(o("LOG_HI"), o("LOG_LO"))
+    assert h("LOG_INVC") == o("LOG_INVC")
+    assert h("EXP_C_LIST") == o("EXP_C") and h("LOG_C_LIST") == o("LOG_C")
+    for k in ("LN2_HI", "LN2_LO", "RCP_HI", "RCP_LO", "INV_L", "L1", "L2", "LN2X_HI", "LN2X_LO",
+              "EXP_XMAX", "EXPM1_XMAX", "EXP_XLO", "EXPM1_XNEG", "EXPM1_TINY", "LOG1P_TINY"):
+        assert h(k) == o(k), k
+    for k in ("L", "K", "N", "N1", "E_OFF", "E_CNT", "C_OFF", "C_CNT", "CM1_OFF", "CM1_CNT"):
+        assert h(k) == o(k), k
