@@ -86,8 +86,8 @@ def cpu_baseline(inputs64, sample):
         getattr(oracle, fn)(a0, a1, threads=threads)
         t += time.perf_counter() - t0
     return {"value": 4 * sample / t / 1e9, "unit": "Gelem/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d elements of each of the 4 binary64 arrays (%d elements), "
-                      "scalar oracle, OpenMP static schedule" % (sample, 4 * sample),
+            "sample": "the first %d elements of each of the 4 binary64 benchmark arrays "
+                      "(%d elements), scalar oracle, OpenMP static schedule" % (sample, 4 * sample),
             "seconds": t}
 
 
@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 rates")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 24)
+    ap.add_argument("--cpu-sample", type=int, default=N)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the functions are "

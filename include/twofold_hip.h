@@ -91,6 +91,18 @@ tf_status tf_expm1_1xf(const float* x, float* z, size_t n, void* stream);
 tf_status tf_log1xf(const float* x, float* z, size_t n, void* stream);
 tf_status tf_log1p_1xf(const float* x, float* z, size_t n, void* stream);
 
+/* --- launch configuration (used by the autotuner) ----------------------
+ * fn: 0 texp, 1 texpm1, 2 tlog, 3 tlog1p, 4 exp1x, 5 expm1_1x, 6 log1x,
+ * 7 log1p_1x; dtype: 0 binary64, 1 binary32.  ept: elements per thread
+ * (1, 2 or 4; arrays that are not 16-byte aligned always use 1);
+ * blocks_per_cu: workgroups of 256 threads per compute unit in the grid
+ * (0 = as many as are resident at once); prefetch: tiles kept in flight
+ * ahead of the one being evaluated (1 or 2; the 1x kernels ignore it).
+ * Process-wide setting, not thread-safe against concurrent launches;
+ * TF_EINVAL for out-of-range values. */
+tf_status tf_set_launch_config(int fn, int dtype, int ept, int blocks_per_cu, int prefetch);
+tf_status tf_get_launch_config(int fn, int dtype, int* ept, int* blocks_per_cu, int* prefetch);
+
 /* --- library information ---------------------------------------------- */
 const char* tf_status_string(tf_status s);
 const char* tf_version(void);

@@ -48,6 +48,10 @@ def _load():
             fn = getattr(lib, "tf_" + f + sfx)
             fn.argtypes = [P, P, S, P]
             fn.restype = ctypes.c_int
+    lib.tf_set_launch_config.argtypes = [ctypes.c_int] * 5
+    lib.tf_set_launch_config.restype = ctypes.c_int
+    lib.tf_get_launch_config.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
+    lib.tf_get_launch_config.restype = ctypes.c_int
     lib.tf_status_string.argtypes = [ctypes.c_int]
     lib.tf_status_string.restype = ctypes.c_char_p
     lib.tf_version.restype = ctypes.c_char_p
@@ -128,3 +132,24 @@ def onex_call(name, x, out=None):
     with torch.cuda.device(x.device):
         _check(fn(x.data_ptr(), z.data_ptr(), x.numel(), _stream()), "tf_" + name)
     return z
+
+
+FN_IDS = {name: i for i, name in enumerate(TWOFOLD + ONEX)}
+DTYPE_IDS = {"f64": 0, "f32": 1}
+
+
+def set_launch_config(fn, dtype, ept, blocks_per_cu, prefetch=1):
+    """Launch configuration of one (function, dtype): elements per thread
+    (1, 2, 4), workgroups per compute unit (0 = all that are resident) and
+    tiles prefetched ahead (1, 2)."""
+    _check(_load().tf_set_launch_config(FN_IDS[fn], DTYPE_IDS[dtype], ept, blocks_per_cu,
+                                        prefetch), "tf_set_launch_config")
+
+
+def get_launch_config(fn, dtype):
+    e = ctypes.c_int()
+    b = ctypes.c_int()
+    p = ctypes.c_int()
+    _check(_load().tf_get_launch_config(FN_IDS[fn], DTYPE_IDS[dtype], ctypes.byref(e),
+                                        ctypes.byref(b), ctypes.byref(p)), "tf_get_launch_config")
+    return e.value, b.value, p.value

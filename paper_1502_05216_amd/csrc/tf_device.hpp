@@ -197,11 +197,23 @@ template <class T> __device__ __forceinline__ T log_q(T r) {
     return q;
 }
 
+// Every per-element routine below has a FAST form.  A kernel takes it for a
+// whole wave when every lane of the wave satisfies the routine's stated
+// argument condition (a wave vote); under that condition the range, NaN and
+// infinity selects of the general form are no-ops, so both forms give the same
+// bits.  This is the paper's conditional vectoring: the plain branch-free
+// computation when all lanes lie in the main interval, the general one
+// otherwise.
+
 // exp(x): x = (32m + j) ln2/32 + r, e^x = 2^m 2^(j/32) e^r.
-template <class T> __device__ __forceinline__ T exp1x(T x, ExpTab<T> t) {
+// FAST: EXP_XLO <= x <= EXP_XMAX.
+template <bool FAST, class T> __device__ __forceinline__ T exp1x(T x, ExpTab<T> t) {
     using K = P<T>;
-    T xc = (x >= K::EXP_XLO) ? x : K::EXP_XLO;
-    xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
+    T xc = x;
+    if constexpr (!FAST) {
+        xc = (x >= K::EXP_XLO) ? x : K::EXP_XLO;
+        xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
+    }
     T kd = frint(xc * K::INV_L);
     int k = (int)kd;
     T r = ffma(-kd, K::L1, xc);
@@ -211,6 +223,7 @@ template <class T> __device__ __forceinline__ T exp1x(T x, ExpTab<T> t) {
     typename K::V2 s = t.S[j];
     T y = s.x + ffma(s.x, p, s.y);
     T res = fldexp(y, m);
+    if constexpr (FAST) return res;
     res = (x < K::EXP_XLO) ? T(0) : res;
     res = (x > K::EXP_XMAX) ? K::INF : res;
     return isnan_(x) ? x + x : res;
@@ -222,11 +235,14 @@ template <class T> __device__ __forceinline__ T expm1_tiny(T x) {
 }
 
 // expm1(x): the reduction of exp with r = rhi + rlo; the -1 enters as -2^-m in
-// the scaled domain through exact transforms.
-template <class T> __device__ __forceinline__ T expm1_1x(T x, ExpTab<T> t) {
+// the scaled domain through exact transforms.  FAST: EXPM1_XNEG <= x <= EXPM1_XMAX.
+template <bool FAST, class T> __device__ __forceinline__ T expm1_1x(T x, ExpTab<T> t) {
     using K = P<T>;
-    T xc = (x >= K::EXPM1_XNEG) ? x : K::EXPM1_XNEG;
-    xc = (xc <= K::EXPM1_XMAX) ? xc : K::EXPM1_XMAX;
+    T xc = x;
+    if constexpr (!FAST) {
+        xc = (x >= K::EXPM1_XNEG) ? x : K::EXPM1_XNEG;
+        xc = (xc <= K::EXPM1_XMAX) ? xc : K::EXPM1_XMAX;
+    }
     T kd = frint(xc * K::INV_L);
     int k = (int)kd;
     T rhi = ffma(-kd, K::L1, xc);
@@ -242,6 +258,7 @@ template <class T> __device__ __forceinline__ T expm1_1x(T x, ExpTab<T> t) {
     T tail = H.x1 + ((A.x1 + B.x1) + c);
     T res = fldexp(H.x0 + tail, m);
     res = (fabs_(x) < K::EXPM1_TINY) ? expm1_tiny(x) : res;
+    if constexpr (FAST) return res;
     res = (x < K::EXPM1_XNEG) ? T(-1) : res;
     res = (x > K::EXPM1_XMAX) ? K::INF : res;
     return isnan_(x) ? x + x : res;
@@ -260,7 +277,8 @@ template <class T> __device__ __forceinline__ LogSplit<T> log_split(T u) {
 }
 
 // log(x) = e ln2 - log(invc) + log1p(z invc - 1), z invc - 1 exact.
-template <class T> __device__ __forceinline__ T log1x(T x, LogTab<T> t) {
+// FAST: 0 < x < inf.
+template <bool FAST, class T> __device__ __forceinline__ T log1x(T x, LogTab<T> t) {
     using K = P<T>;
     bool sub = x < K::MIN_NORMAL;
     T xs = sub ? fldexp(x, K::SUBSCALE) : x;
@@ -274,6 +292,7 @@ template <class T> __device__ __forceinline__ T log1x(T x, LogTab<T> t) {
     T tail = ffma(r * r, log_q(r), lo);
     Tw<T> st = fast_two_sum(hi, r);
     T res = st.x0 + (st.x1 + tail);
+    if constexpr (FAST) return res;
     res = (x == K::INF) ? K::INF : res;
     res = (x == T(0)) ? -K::INF : res;
     res = (x < T(0)) ? K::qnan() : res;
@@ -281,8 +300,8 @@ template <class T> __device__ __forceinline__ T log1x(T x, LogTab<T> t) {
 }
 
 // log1p(x): u + c = 1 + x exactly, log(u) with c folded into r; |x| < 2^-8
-// uses r = x directly.
-template <class T> __device__ __forceinline__ T log1p_1x(T x, LogTab<T> t) {
+// uses r = x directly.  FAST: -1 < x < inf.
+template <bool FAST, class T> __device__ __forceinline__ T log1p_1x(T x, LogTab<T> t) {
     using K = P<T>;
     Tw<T> u = two_sum(T(1), x);
     LogSplit<T> ls = log_split(u.x0);
@@ -300,6 +319,7 @@ template <class T> __device__ __forceinline__ T log1p_1x(T x, LogTab<T> t) {
     Tw<T> st = fast_two_sum(hi, rhi);
     T res = st.x0 + (st.x1 + tail);
     res = (fabs_(x) < K::LOG1P_TINY) ? x : res;
+    if constexpr (FAST) return res;
     res = (x == K::INF) ? K::INF : res;
     res = (x == T(-1)) ? -K::INF : res;
     res = (x < T(-1)) ? K::qnan() : res;
@@ -320,7 +340,7 @@ template <class T> __device__ __forceinline__ Tw<T> horner_exp(T y) {
     return p;
 }
 
-template <class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab<T> t) {
+template <bool FAST, class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab<T> t) {
     using K = P<T>;
     constexpr int SH = K::L + K::K;
     T Md = frint(x * T(1 << K::K));
@@ -330,9 +350,10 @@ template <class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab
     int m = a >> SH, n = a & ((1 << SH) - 1);
     m = M < 0 ? -m : m;
     n = M < 0 ? -n : n;
-    // callers pass x in [EXP_XLO, EXP_XMAX], where these clamps do nothing
-    m = m < -K::E_OFF ? -K::E_OFF : (m > K::E_CNT - 1 - K::E_OFF ? K::E_CNT - 1 - K::E_OFF : m);
-    n = n < -K::C_OFF ? -K::C_OFF : (n > K::C_OFF ? K::C_OFF : n);
+    if constexpr (!FAST) {  // callers pass x in [EXP_XLO, EXP_XMAX]: these clamps do nothing
+        m = m < -K::E_OFF ? -K::E_OFF : (m > K::E_CNT - 1 - K::E_OFF ? K::E_CNT - 1 - K::E_OFF : m);
+        n = n < -K::C_OFF ? -K::C_OFF : (n > K::C_OFF ? K::C_OFF : n);
+    }
     Tw<T> Tt = horner_exp(y);
     typename K::V2 e2 = t.E[m + K::E_OFF];
     typename K::V2 c2 = t.C[n + K::C_OFF];
@@ -343,17 +364,20 @@ template <class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab
 
 // pexpm10 small path, |x| <= 89.5/128: x = n/128 + y, T = (e^y - 1) via the
 // Horner of N1 without its last term, times y and the twofold 1/N1!,
-// Z = (C + T) + C T with C = e^(n/128) - 1.
-template <class T> __device__ __forceinline__ Tw<T> pexpm10_small(T x, Pm1Tab<T> t) {
+// Z = (C + T) + C T with C = e^(n/128) - 1.  FAST: |x| <= 89/128.
+template <bool FAST, class T> __device__ __forceinline__ Tw<T> pexpm10_small(T x, Pm1Tab<T> t) {
     using K = P<T>;
     constexpr int N1 = K::N1;
-    // Valid arguments satisfy |x| <= ln 2 + tiny < 89/128; anything else (NaN,
-    // inf from an invalid lane) is replaced so the index stays in [-89, 89].
-    T xs = (fabs_(x) <= T(0.6953125)) ? x : T(0);
+    T xs = x;
+    if constexpr (!FAST) {
+        // Valid arguments satisfy |x| <= ln 2 + tiny < 89/128; anything else (NaN,
+        // inf from an invalid lane) is replaced so the index stays in [-89, 89].
+        xs = (fabs_(x) <= T(0.6953125)) ? x : T(0);
+    }
     T nd = frint(xs * T(128));
     T y = ffma(-nd, T(1.0 / 128), xs);                  // exact
     int n = (int)nd;
-    n = n < -K::CM1_OFF ? -K::CM1_OFF : (n > K::CM1_OFF ? K::CM1_OFF : n);
+    if constexpr (!FAST) n = n < -K::CM1_OFF ? -K::CM1_OFF : (n > K::CM1_OFF ? K::CM1_OFF : n);
     Tw<T> p = fast_two_sum(T(N1), y);
 #pragma unroll
     for (int j = N1 - 2; j >= 1; --j) p = add_td_fast(mul_td(p, y), T(fact_ratio(N1, j)));
@@ -375,55 +399,100 @@ template <class T> __device__ __forceinline__ T special_rule(T z0, T z1) {
 // active lanes have |x1| < EXPM1_TINY, so expm1(x1) is its tiny branch.
 // ----------------------------------------------------------------------------
 template <class T> __device__ __forceinline__ T expm1_of_x1(T x1, bool x1_tiny, ExpTab<T> et) {
-    return x1_tiny ? expm1_tiny(x1) : expm1_1x(x1, et);
+    return x1_tiny ? expm1_tiny(x1) : expm1_1x<false>(x1, et);
 }
 
-template <class T>
+// Fast-wave conditions (checked per lane, voted per wave).
+template <class T> __device__ __forceinline__ bool texp_fast_arg(T x0, T x1) {
+    return x0 >= P<T>::EXP_XLO && x0 <= P<T>::EXP_XMAX && fabs_(x1) < P<T>::EXPM1_TINY;
+}
+template <class T> __device__ __forceinline__ bool texpm1_fast_arg(T x0, T x1) {
+    return x0 >= P<T>::EXPM1_XNEG && x0 <= P<T>::EXPM1_XMAX && fabs_(x1) < P<T>::EXPM1_TINY;
+}
+template <class T> __device__ __forceinline__ bool tlog_fast_arg(T y0, T y1) {
+    T s = y0 + y1;
+    return y0 > T(0) && y0 < P<T>::INF && s > T(0) && s < P<T>::INF;
+}
+template <class T> __device__ __forceinline__ bool tlog1p_fast_arg(T y0, T y1) {
+    T s = y0 + y1;
+    return y0 > T(-1) && y0 < P<T>::INF && s > T(-1) && s < P<T>::INF;
+}
+
+// texp.  FAST: texp_fast_arg (then z0 is finite and pexp0 is in range).
+template <bool FAST, class T>
 __device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et, Pexp0Tab<T> pt,
                                           T& z0o, T& z1o) {
     using K = P<T>;
-    T z0 = exp1x(x0, et);
-    T t1 = expm1_of_x1(x1, x1_tiny, et);
-    bool in = x0 >= K::EXP_XLO;                       // below: pexp0 gives (0, 0)
-    T xc = in ? x0 : K::EXP_XLO;
-    xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
-    Scaled<T> s = pexp0_core(xc, pt);
-    T v0 = in ? s.v.x0 : T(0);
-    T v1 = in ? s.v.x1 : T(0);
-    int k = in ? s.k : 0;
-    T z0s = fldexp(z0, -k);                           // exact
-    T z1s = z0s * t1 + (v1 + (v0 - z0s));
-    z0o = z0;
-    z1o = special_rule(z0, fldexp(z1s, k));
+    if constexpr (FAST) {
+        T z0 = exp1x<true>(x0, et);
+        T t1 = expm1_tiny(x1);
+        Scaled<T> s = pexp0_core<true>(x0, pt);
+        T z0s = fldexp(z0, -s.k);                     // exact
+        T z1s = z0s * t1 + (s.v.x1 + (s.v.x0 - z0s));
+        z0o = z0;
+        z1o = fldexp(z1s, s.k);
+    } else {
+        T z0 = exp1x<false>(x0, et);
+        T t1 = expm1_of_x1(x1, x1_tiny, et);
+        bool in = x0 >= K::EXP_XLO;                   // below: pexp0 gives (0, 0)
+        T xc = in ? x0 : K::EXP_XLO;
+        xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
+        Scaled<T> s = pexp0_core<false>(xc, pt);
+        T v0 = in ? s.v.x0 : T(0);
+        T v1 = in ? s.v.x1 : T(0);
+        int k = in ? s.k : 0;
+        T z0s = fldexp(z0, -k);                       // exact
+        T z1s = z0s * t1 + (v1 + (v0 - z0s));
+        z0o = z0;
+        z1o = special_rule(z0, fldexp(z1s, k));
+    }
 }
 
+// texpm1, general form: small path pexpm10, and pexp0(x0) - 1 for |x0| > ln 2
+// on the waves that hold such a lane.
 template <class T>
 __device__ __forceinline__ void texpm1_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et, Pexp0Tab<T> pt,
                                             Pm1Tab<T> mt, T& z0o, T& z1o) {
     using K = P<T>;
-    T z0 = expm1_1x(x0, et);
+    T z0 = expm1_1x<false>(x0, et);
     T t1 = expm1_of_x1(x1, x1_tiny, et);
     bool small = fabs_(x0) <= K::LN2_HI;
-    Tw<T> w = pexpm10_small(small ? x0 : T(0), mt);
+    Tw<T> w = pexpm10_small<false>(small ? x0 : T(0), mt);
     bool big = !small && x0 >= K::EXP_XLO && x0 <= K::EXP_XMAX;
     if (__any(big)) {                                 // pexp0(x0) - 1 on this wave
         T xc = big ? x0 : T(1);
-        Scaled<T> s = pexp0_core(xc, pt);
+        Scaled<T> s = pexp0_core<false>(xc, pt);
         Tw<T> wl = add_td(Tw<T>{fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k)}, T(-1));
-        w = big ? wl : w;
+        w = sel(big, wl, w);
     }
-    w = (x0 < K::EXP_XLO) ? Tw<T>{T(-1), T(0)} : w;  // pexp0 = (0, 0) below range
+    w = sel(x0 < K::EXP_XLO, Tw<T>{T(-1), T(0)}, w);  // pexp0 = (0, 0) below range
     T z1 = (z0 + T(1)) * t1 + (w.x1 + (w.x0 - z0));
     z0o = z0;
     z1o = special_rule(z0, z1);
 }
 
-// Newton step shared by plog and plog1p: r0 = log1p(a0 + a1), s = pexpm10(-r0),
-// u = ((a s) + a) + s, r1 = u0 + u1.
+// texpm1 on a fast wave (texpm1_fast_arg on every lane), small path only.
+// Returns true for a lane with |x0| > ln 2, whose z0, z1 are not computed here:
+// the kernel hands that lane to texpm1_elem later.
 template <class T>
+__device__ __forceinline__ bool texpm1_small_fast(T x0, T x1, ExpTab<T> et, Pm1Tab<T> mt, T& z0o,
+                                                  T& z1o) {
+    using K = P<T>;
+    bool small = fabs_(x0) <= K::LN2_HI;
+    T z0 = expm1_1x<true>(x0, et);
+    T t1 = expm1_tiny(x1);
+    Tw<T> w = pexpm10_small<true>(small ? x0 : T(0), mt);
+    z0o = z0;
+    z1o = (z0 + T(1)) * t1 + (w.x1 + (w.x0 - z0));
+    return !small;
+}
+
+// Newton step shared by plog and plog1p: r0 = log1p(a0 + a1), s = pexpm10(-r0),
+// u = ((a s) + a) + s, r1 = u0 + u1.  FAST: a0 + a1 finite.
+template <bool FAST, class T>
 __device__ __forceinline__ Tw<T> plog_newton(Tw<T> a, LogTab<T> lt, Pm1Tab<T> mt) {
-    T r0 = log1p_1x(a.x0 + a.x1, lt);
-    Tw<T> s = pexpm10_small(-r0, mt);
+    T r0 = log1p_1x<FAST>(a.x0 + a.x1, lt);
+    Tw<T> s = pexpm10_small<FAST>(-r0, mt);
     Tw<T> u = add_tt(add_tt(mul_tt(a, s), a), s);
     return {r0, u.x0 + u.x1};
 }
@@ -432,13 +501,13 @@ template <class T> __device__ __forceinline__ Tw<T> add_n_ln2(Tw<T> X, int n) {
     return add_tt(X, mul_td(Tw<T>{P<T>::LN2_HI, P<T>::LN2_LO}, (T)n));
 }
 
-// w = 2^n z: frexp when w0 < 1/2 or w0 > 2, else n = 0.
+// w = 2^n z: frexp when w0 < 1/2 or w0 > 2, else n = 0.  Scaling w0 by
+// 2^-n with n its frexp exponent gives frexp's mantissa exactly (subnormals
+// included), and scaling by 2^0 is the identity, so one select of n suffices.
 template <class T> __device__ __forceinline__ Tw<T> log_scale(Tw<T> w, int& n) {
     bool need = w.x0 < T(0.5) || w.x0 > T(2);
-    int ne = frexp_exp(w.x0);
-    Tw<T> z = {frexp_mant(w.x0), fldexp(w.x1, -ne)};
-    n = need ? ne : 0;
-    return sel(need, z, w);
+    n = need ? frexp_exp(w.x0) : 0;
+    return {fldexp(w.x0, -n), fldexp(w.x1, -n)};
 }
 
 // x1 of a log whose renormalised argument w0 is outside (0, inf).
@@ -448,40 +517,55 @@ template <class T> __device__ __forceinline__ T log_domain_x1(T w0, T x1) {
     return (w0 < T(0) || isnan_(w0)) ? P<T>::qnan() : x1;
 }
 
-template <class T>
+// tlog.  FAST: tlog_fast_arg (y0 and y0 + y1 positive and finite).
+template <bool FAST, class T>
 __device__ __forceinline__ void tlog_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o, T& x1o) {
-    T x0 = log1x(y0, lt);
+    T x0 = log1x<FAST>(y0, lt);
     Tw<T> v = two_sum(y0, y1);
     int n;
     Tw<T> z = log_scale(v, n);
     Tw<T> a = {z.x0 - T(1), z.x1};                    // exact
-    Tw<T> X = add_n_ln2(plog_newton(a, lt, mt), n);
+    Tw<T> X = add_n_ln2(plog_newton<FAST>(a, lt, mt), n);
     T x1 = X.x1 + (X.x0 - x0);
-    x1 = log_domain_x1(v.x0, x1);
     x0o = x0;
-    x1o = special_rule(x0, x1);
+    if constexpr (FAST) {
+        x1o = x1;
+    } else {
+        x1 = log_domain_x1(v.x0, x1);
+        x1o = special_rule(x0, x1);
+    }
 }
 
-template <class T>
+// tlog1p.  FAST: tlog1p_fast_arg (y0 and y0 + y1 above -1 and finite).
+template <bool FAST, class T>
 __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o,
                                             T& x1o) {
     using K = P<T>;
-    T x0 = log1p_1x(y0, lt);
+    T x0 = log1p_1x<FAST>(y0, lt);
     Tw<T> v = two_sum(y0, y1);
     bool outer = v.x0 < T(-0.5) || v.x0 > T(1);
-    Tw<T> w = add_td(v, T(1));
-    w = two_sum(w.x0, w.x1);                          // renormalised 1 + y
-    int nn;
-    Tw<T> z = log_scale(w, nn);
-    Tw<T> a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
-    Tw<T> R = plog_newton(a, lt, mt);
-    Tw<T> X = sel(outer, add_n_ln2(R, outer ? nn : 0), R);
+    Tw<T> a = v;
+    Tw<T> w = v;
+    int nn = 0;
+    const bool any_outer = __any(outer);
+    if (any_outer) {                                  // log of the renormalised 1 + y
+        w = add_td(v, T(1));
+        w = two_sum(w.x0, w.x1);
+        Tw<T> z = log_scale(w, nn);
+        a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
+    }
+    Tw<T> X = plog_newton<FAST>(a, lt, mt);
+    if (any_outer) X = sel(outer, add_n_ln2(X, outer ? nn : 0), X);
     T x1 = X.x1 + (X.x0 - x0);
-    x1 = outer ? log_domain_x1(w.x0, x1) : x1;
-    x1 = (v.x0 == K::INF) ? K::INF : x1;
-    x1 = isnan_(v.x0) ? K::qnan() : x1;
     x0o = x0;
-    x1o = special_rule(x0, x1);
+    if constexpr (FAST) {
+        x1o = x1;
+    } else {
+        x1 = (outer && any_outer) ? log_domain_x1(w.x0, x1) : x1;
+        x1 = (v.x0 == K::INF) ? K::INF : x1;
+        x1 = isnan_(v.x0) ? K::qnan() : x1;
+        x1o = special_rule(x0, x1);
+    }
 }
 
 }  // namespace tfh

@@ -94,50 +94,271 @@ template <class T> struct LdsFor<T, FN_TLOG1P> { using type = Lds<T, false, fals
 // every function, so tail lanes never pull a wave onto a slow path.
 template <class T> __device__ __forceinline__ T pad_arg() { return T(0.5); }
 
-template <class T, int FN, class L>
-__device__ __forceinline__ void eval(const L& lds, T a, T b, bool x1_tiny, T& r0, T& r1) {
-    if constexpr (FN == FN_TEXP) {
-        texp_elem(a, b, x1_tiny, lds.et(), lds.pt(), r0, r1);
-    } else if constexpr (FN == FN_TEXPM1) {
-        texpm1_elem(a, b, x1_tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
-    } else if constexpr (FN == FN_TLOG) {
-        tlog_elem(a, b, lds.lt(), lds.mt(), r0, r1);
+// EPT consecutive elements of one thread.
+template <class T, int EPT> struct Vec { T v[EPT]; };
+
+// 16-byte vector load/store of a thread's EPT consecutive elements (the
+// pointer is 16-byte aligned: the host checks the base pointers).  Built with
+// -DTF_NONTEMPORAL=1 the streams use non-temporal accesses (no reuse).
+#ifndef TF_NONTEMPORAL
+#define TF_NONTEMPORAL 0
+#endif
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T, int EPT> __device__ __forceinline__ void vload(Vec<T, EPT>& r, const T* p) {
+    if constexpr ((sizeof(T) * EPT) % 16 == 0) {
+        constexpr int Q = sizeof(T) * EPT / 16, PER = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const u32x4* src = reinterpret_cast<const u32x4*>(p) + k;
+            u32x4 q = TF_NONTEMPORAL ? __builtin_nontemporal_load(src) : *src;
+            __builtin_memcpy(&r.v[k * PER], &q, 16);
+        }
     } else {
-        tlog1p_elem(a, b, lds.lt(), lds.mt(), r0, r1);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) r.v[e] = p[e];
+    }
+}
+template <class T, int EPT> __device__ __forceinline__ void vstore(T* p, const Vec<T, EPT>& r) {
+    if constexpr ((sizeof(T) * EPT) % 16 == 0) {
+        constexpr int Q = sizeof(T) * EPT / 16, PER = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            u32x4 q;
+            __builtin_memcpy(&q, &r.v[k * PER], 16);
+            u32x4* dst = reinterpret_cast<u32x4*>(p) + k;
+            if (TF_NONTEMPORAL) __builtin_nontemporal_store(q, dst);
+            else *dst = q;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) p[e] = r.v[e];
     }
 }
 
-// Twofold kernel: EPT elements per thread per tile, element index
-// tile + e*blockDim + tid so each load/store instruction is coalesced.
-template <class T, int FN, int EPT>
+template <class T, int FN> __device__ __forceinline__ bool fast_arg(T a, T b) {
+    if constexpr (FN == FN_TEXP) return texp_fast_arg(a, b);
+    else if constexpr (FN == FN_TEXPM1) return texpm1_fast_arg(a, b);
+    else if constexpr (FN == FN_TLOG) return tlog_fast_arg(a, b);
+    else return tlog1p_fast_arg(a, b);
+}
+
+// General form of one element (any argument).
+template <class T, int FN, class L>
+__device__ __forceinline__ void eval_general(const L& lds, T a, T b, bool x1_tiny, T& r0, T& r1) {
+    if constexpr (FN == FN_TEXP) texp_elem<false>(a, b, x1_tiny, lds.et(), lds.pt(), r0, r1);
+    else if constexpr (FN == FN_TEXPM1) texpm1_elem(a, b, x1_tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
+    else if constexpr (FN == FN_TLOG) tlog_elem<false>(a, b, lds.lt(), lds.mt(), r0, r1);
+    else tlog1p_elem<false>(a, b, lds.lt(), lds.mt(), r0, r1);
+}
+
+// Evaluates a thread's EPT elements.  Returns true when the wave took the fast
+// form; for texpm1 the fast form leaves the |x0| > ln 2 lanes to the caller
+// (bit e of *deferred set for such an element).
+template <class T, int FN, int EPT, class L>
+__device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, const Vec<T, EPT>& b,
+                                          Vec<T, EPT>& r0, Vec<T, EPT>& r1, unsigned* deferred) {
+    bool fast = true, tiny = true;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        fast = fast && fast_arg<T, FN>(a.v[e], b.v[e]);
+        tiny = tiny && (fabs_(b.v[e]) < P<T>::EXPM1_TINY);
+    }
+    *deferred = 0;
+    if (__all(fast)) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            if constexpr (FN == FN_TEXP) {
+                texp_elem<true>(a.v[e], b.v[e], true, lds.et(), lds.pt(), r0.v[e], r1.v[e]);
+            } else if constexpr (FN == FN_TEXPM1) {
+                if (texpm1_small_fast(a.v[e], b.v[e], lds.et(), lds.mt(), r0.v[e], r1.v[e]))
+                    *deferred |= 1u << e;
+            } else if constexpr (FN == FN_TLOG) {
+                tlog_elem<true>(a.v[e], b.v[e], lds.lt(), lds.mt(), r0.v[e], r1.v[e]);
+            } else {
+                tlog1p_elem<true>(a.v[e], b.v[e], lds.lt(), lds.mt(), r0.v[e], r1.v[e]);
+            }
+        }
+        return true;
+    }
+    const bool x1_tiny = __all(tiny);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) eval_general<T, FN>(lds, a.v[e], b.v[e], x1_tiny, r0.v[e], r1.v[e]);
+    return false;
+}
+
+// Per-wave queue of deferred elements (texpm1 with |x0| > ln 2): the element
+// index and its two argument parts in LDS, appended with a ballot prefix count
+// and drained 64 at a time with one element per lane, so pexp0 runs on full
+// waves and the drain reads no global memory.
+template <class T, int CAP> struct WaveQueue {
+    size_t* qi;   // this wave's slots: index, x0, x1
+    T* qa;
+    T* qb;
+    int n;        // entries in use (wave-uniform)
+
+    __device__ void push(bool on, size_t idx, T a, T b) {
+        const unsigned long long m = __ballot(on);
+        const int lane_off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (on) {
+            qi[n + lane_off] = idx;
+            qa[n + lane_off] = a;
+            qb[n + lane_off] = b;
+        }
+        n += __popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // Takes min(n, 64) entries: lane l gets entry l (valid if l < taken).
+    __device__ int pop64(int lane, size_t* idx, T* a, T* b) {
+        const int taken = n < 64 ? n : 64;
+        if (lane < taken) {
+            *idx = qi[lane];
+            *a = qa[lane];
+            *b = qb[lane];
+        }
+#pragma unroll
+        for (int k = 1; k * 64 < CAP; ++k) {
+            const int src = k * 64 + lane;
+            if (src < n) {
+                qi[src - 64] = qi[src];
+                qa[src - 64] = qa[src];
+                qb[src - 64] = qb[src];
+            }
+        }
+        n -= taken;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        return taken;
+    }
+};
+
+// Drains up to 64 deferred texpm1 elements with the general form; their z0
+// was already stored by the fast pass, only z1 is written here.
+template <class T, class L, int CAP>
+__device__ __forceinline__ void drain_texpm1(const L& lds, WaveQueue<T, CAP>& wq, int lane,
+                                             T* z1) {
+    size_t i = 0;
+    T a = T(1), b = T(0);
+    const int taken = wq.pop64(lane, &i, &a, &b);
+    if (lane < taken) {
+        const bool tiny = __all(fabs_(b) < P<T>::EXPM1_TINY);
+        T r0, r1;
+        texpm1_elem(a, b, tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
+        z1[i] = r1;
+    }
+}
+
+// Twofold kernel.  A tile is kBlock*EPT consecutive elements, thread t owning
+// elements t*EPT .. t*EPT+EPT-1 (16-byte loads and stores, each wave touching
+// one contiguous 64*EPT*sizeof(T) span).  Workgroups walk the full tiles with a
+// grid stride and keep the next PD tiles in flight (loaded into registers
+// before the current tile is evaluated), so HBM latency overlaps arithmetic.
+// The ragged remainder (< one tile) is done by one workgroup with per-element
+// guards and the general form.
+template <class T, int FN, int EPT, int PD>
 __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T* z0, T* z1,
                                                     size_t n) {
+    constexpr bool QUEUE = FN == FN_TEXPM1;
+    constexpr int QCAP = 64 + 64 * EPT;   // < 64 left after a drain, + one tile
+    constexpr int QW = QUEUE ? kBlock / 64 : 1, QC = QUEUE ? QCAP : 1;
     __shared__ typename LdsFor<T, FN>::type lds;
+    __shared__ size_t q_idx[QW][QC];
+    __shared__ T q_x0[QW][QC];
+    __shared__ T q_x1[QW][QC];
     lds.load();
     __syncthreads();
-    const size_t tile = (size_t)blockDim.x * EPT;
-    for (size_t base = (size_t)blockIdx.x * tile; base < n; base += (size_t)gridDim.x * tile) {
-        T a[EPT], b[EPT], r0[EPT], r1[EPT];
-        bool tiny = true;
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t nfull = n / TILE;
+    const size_t stride = gridDim.x;
+    const size_t off = (size_t)threadIdx.x * EPT;
+    const int lane = threadIdx.x & 63;
+    const int w = QUEUE ? threadIdx.x / 64 : 0;
+    WaveQueue<T, QCAP> wq{q_idx[w], q_x0[w], q_x1[w], 0};
+    Vec<T, EPT> a[PD + 1], b[PD + 1], r0, r1;
+#pragma unroll
+    for (int s = 0; s <= PD; ++s) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            size_t i = base + (size_t)e * blockDim.x + threadIdx.x;
-            a[e] = i < n ? x0[i] : pad_arg<T>();
-            b[e] = i < n ? x1[i] : T(0);
-            tiny = tiny && (fabs_(b[e]) < P<T>::EXPM1_TINY);
+            a[s].v[e] = pad_arg<T>();
+            b[s].v[e] = T(0);
         }
-        bool x1_tiny = __all(tiny);
+    }
+    size_t t = blockIdx.x;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) eval<T, FN>(lds, a[e], b[e], x1_tiny, r0[e], r1[e]);
+    for (int s = 0; s < PD; ++s) {
+        const size_t ts = t + (size_t)s * stride;
+        if (ts < nfull) {
+            vload(a[s], x0 + ts * TILE + off);
+            vload(b[s], x1 + ts * TILE + off);
+        }
+    }
+    for (; t < nfull; t += stride) {
+        const size_t tn = t + (size_t)PD * stride;
+        if (tn < nfull) {
+            vload(a[PD], x0 + tn * TILE + off);
+            vload(b[PD], x1 + tn * TILE + off);
+        }
+        unsigned deferred;
+        eval_tile<T, FN, EPT>(lds, a[0], b[0], r0, r1, &deferred);
+        const size_t base = t * TILE + off;
+        vstore(z0 + base, r0);
+        if (QUEUE && __any(deferred != 0)) {
+            // z1 of deferred elements is written by the drain, not here
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const bool d = (deferred >> e) & 1u;
+                if (!d) z1[base + e] = r1.v[e];
+                wq.push(d, base + e, a[0].v[e], b[0].v[e]);
+            }
+            while (wq.n >= 64) drain_texpm1<T>(lds, wq, lane, z1);
+        } else {
+            vstore(z1 + base, r1);
+        }
+#pragma unroll
+        for (int s = 0; s < PD; ++s) {
+            a[s] = a[s + 1];
+            b[s] = b[s + 1];
+        }
+    }
+    if constexpr (QUEUE) {
+        while (wq.n > 0) drain_texpm1<T>(lds, wq, lane, z1);
+    }
+    const size_t rbase = nfull * TILE;
+    if (rbase < n && blockIdx.x == nfull % stride) {
+        bool tiny = true;
+        Vec<T, EPT> ra, rb;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            size_t i = base + (size_t)e * blockDim.x + threadIdx.x;
+            size_t i = rbase + off + e;
+            ra.v[e] = i < n ? x0[i] : pad_arg<T>();
+            rb.v[e] = i < n ? x1[i] : T(0);
+            tiny = tiny && (fabs_(rb.v[e]) < P<T>::EXPM1_TINY);
+        }
+        const bool x1_tiny = __all(tiny);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            eval_general<T, FN>(lds, ra.v[e], rb.v[e], x1_tiny, r0.v[e], r1.v[e]);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            size_t i = rbase + off + e;
             if (i < n) {
-                z0[i] = r0[e];
-                z1[i] = r1[e];
+                z0[i] = r0.v[e];
+                z1[i] = r1.v[e];
             }
         }
     }
+}
+
+template <class T, int F1>
+__device__ __forceinline__ T eval1(const Lds<T, true, false, false, true>& lds, T a) {
+    if constexpr (F1 == F1_EXP) return exp1x<false>(a, lds.et());
+    else if constexpr (F1 == F1_EXPM1) return expm1_1x<false>(a, lds.et());
+    else if constexpr (F1 == F1_LOG) return log1x<false>(a, lds.lt());
+    else return log1p_1x<false>(a, lds.lt());
 }
 
 template <class T, int F1, int EPT>
@@ -145,17 +366,22 @@ __global__ __launch_bounds__(kBlock) void k_onex(const T* x, T* z, size_t n) {
     __shared__ Lds<T, true, false, false, true> lds;
     lds.load();
     __syncthreads();
-    const size_t tile = (size_t)blockDim.x * EPT;
-    for (size_t base = (size_t)blockIdx.x * tile; base < n; base += (size_t)gridDim.x * tile) {
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t nfull = n / TILE;
+    const size_t off = (size_t)threadIdx.x * EPT;
+    for (size_t t = blockIdx.x; t < nfull; t += gridDim.x) {
+        Vec<T, EPT> a, r;
+        vload(a, x + t * TILE + off);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) r.v[e] = eval1<T, F1>(lds, a.v[e]);
+        vstore(z + t * TILE + off, r);
+    }
+    const size_t rbase = nfull * TILE;
+    if (rbase < n && blockIdx.x == nfull % gridDim.x) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            size_t i = base + (size_t)e * blockDim.x + threadIdx.x;
-            T a = i < n ? x[i] : pad_arg<T>();
-            T r;
-            if constexpr (F1 == F1_EXP) r = exp1x(a, lds.et());
-            else if constexpr (F1 == F1_EXPM1) r = expm1_1x(a, lds.et());
-            else if constexpr (F1 == F1_LOG) r = log1x(a, lds.lt());
-            else r = log1p_1x(a, lds.lt());
+            size_t i = rbase + off + e;
+            T r = eval1<T, F1>(lds, i < n ? x[i] : pad_arg<T>());
             if (i < n) z[i] = r;
         }
     }
@@ -187,12 +413,49 @@ tf_status device_cus(int* cus) {
     return TF_OK;
 }
 
-// Grid: enough workgroups to cover n, capped at a few per compute unit
-// (the kernels loop over tiles).
-unsigned grid_for(size_t n, int ept, int cus, int per_cu) {
-    size_t tiles = (n + (size_t)kBlock * ept - 1) / ((size_t)kBlock * ept);
-    size_t cap = (size_t)cus * per_cu;
-    return (unsigned)(tiles < cap ? tiles : cap);
+// Launch configuration per (function, format): elements per thread and
+// workgroups per compute unit (0 = as many as fit, from the occupancy API).
+struct LaunchCfg { int ept; int bpc; int pd; };
+// Defaults measured on MI355X (256 CUs) with paper_1502_05216_amd.tune on
+// 2^26-element arrays (beyond the last-level cache); the landscape is flat,
+// the best few configurations being within a few percent of each other.
+LaunchCfg g_cfg[4][2] = {
+    {{4, 0, 1}, {4, 2, 1}},   // texp     {binary64, binary32}
+    {{1, 4, 1}, {2, 3, 1}},   // texpm1
+    {{2, 8, 1}, {4, 6, 2}},   // tlog
+    {{2, 8, 1}, {2, 0, 1}},   // tlog1p
+};
+LaunchCfg g_cfg1[4][2] = {
+    {{2, 4, 1}, {4, 4, 1}},   // exp1x
+    {{2, 4, 1}, {4, 8, 1}},   // expm1_1x
+    {{2, 4, 1}, {4, 4, 1}},   // log1x
+    {{2, 8, 1}, {4, 8, 1}},   // log1p_1x
+};
+
+template <class K> int blocks_per_cu(K kernel) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kBlock, 0) != hipSuccess ||
+        b <= 0) {
+        (void)hipGetLastError();
+        b = 2;
+    }
+    return b;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <class T, int FN, int EPT, int PD>
+tf_status launch_twofold_ept(const T* x0, const T* x1, T* z0, T* z1, size_t n, int cus, int bpc,
+                             hipStream_t stream) {
+    auto kern = k_twofold<T, FN, EPT, PD>;
+    static int occ = 0;            // per instantiation; benign race (same value)
+    if (occ == 0) occ = blocks_per_cu(kern);
+    const size_t tile = (size_t)kBlock * EPT;
+    size_t tiles = n / tile;
+    size_t cap = (size_t)cus * (bpc > 0 ? bpc : occ);
+    unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, stream, x0, x1, z0, z1, n);
+    return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
 }
 
 template <class T, int FN>
@@ -202,10 +465,31 @@ tf_status launch_twofold(const T* x0, const T* x1, T* z0, T* z1, size_t n, void*
     int cus = 0;
     tf_status st = device_cus(&cus);
     if (st != TF_OK) return st;
-    constexpr int EPT = 2;
-    unsigned grid = grid_for(n, EPT, cus, 8);
-    hipLaunchKernelGGL((k_twofold<T, FN, EPT>), dim3(grid), dim3(kBlock), 0,
-                       (hipStream_t)stream, x0, x1, z0, z1, n);
+    LaunchCfg c = g_cfg[FN][sizeof(T) == 8 ? 0 : 1];
+    // vector loads need 16-byte aligned arrays; otherwise one element per thread
+    if (!(aligned16(x0) && aligned16(x1) && aligned16(z0) && aligned16(z1))) c.ept = 1;
+    hipStream_t s = (hipStream_t)stream;
+    const int key = c.ept * 10 + (c.pd == 2 ? 2 : 1);
+    switch (key) {
+        case 11: return launch_twofold_ept<T, FN, 1, 1>(x0, x1, z0, z1, n, cus, c.bpc, s);
+        case 12: return launch_twofold_ept<T, FN, 1, 2>(x0, x1, z0, z1, n, cus, c.bpc, s);
+        case 41: return launch_twofold_ept<T, FN, 4, 1>(x0, x1, z0, z1, n, cus, c.bpc, s);
+        case 42: return launch_twofold_ept<T, FN, 4, 2>(x0, x1, z0, z1, n, cus, c.bpc, s);
+        case 22: return launch_twofold_ept<T, FN, 2, 2>(x0, x1, z0, z1, n, cus, c.bpc, s);
+        default: return launch_twofold_ept<T, FN, 2, 1>(x0, x1, z0, z1, n, cus, c.bpc, s);
+    }
+}
+
+template <class T, int F1, int EPT>
+tf_status launch_onex_ept(const T* x, T* z, size_t n, int cus, int bpc, hipStream_t stream) {
+    auto kern = k_onex<T, F1, EPT>;
+    static int occ = 0;
+    if (occ == 0) occ = blocks_per_cu(kern);
+    const size_t tile = (size_t)kBlock * EPT;
+    size_t tiles = n / tile;
+    size_t cap = (size_t)cus * (bpc > 0 ? bpc : occ);
+    unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, stream, x, z, n);
     return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
 }
 
@@ -216,11 +500,14 @@ tf_status launch_onex(const T* x, T* z, size_t n, void* stream) {
     int cus = 0;
     tf_status st = device_cus(&cus);
     if (st != TF_OK) return st;
-    constexpr int EPT = 2;
-    unsigned grid = grid_for(n, EPT, cus, 8);
-    hipLaunchKernelGGL((k_onex<T, F1, EPT>), dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       x, z, n);
-    return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
+    LaunchCfg c = g_cfg1[F1][sizeof(T) == 8 ? 0 : 1];
+    if (!(aligned16(x) && aligned16(z))) c.ept = 1;
+    hipStream_t s = (hipStream_t)stream;
+    switch (c.ept) {
+        case 1: return launch_onex_ept<T, F1, 1>(x, z, n, cus, c.bpc, s);
+        case 4: return launch_onex_ept<T, F1, 4>(x, z, n, cus, c.bpc, s);
+        default: return launch_onex_ept<T, F1, 2>(x, z, n, cus, c.bpc, s);
+    }
 }
 
 }  // namespace
@@ -254,6 +541,27 @@ TF_ONEX_ENTRY(tf_exp1xf, float, F1_EXP)
 TF_ONEX_ENTRY(tf_expm1_1xf, float, F1_EXPM1)
 TF_ONEX_ENTRY(tf_log1xf, float, F1_LOG)
 TF_ONEX_ENTRY(tf_log1p_1xf, float, F1_LOG1P)
+
+tf_status tf_set_launch_config(int fn, int dtype, int ept, int blocks_per_cu, int prefetch) {
+    if (fn < 0 || fn > 7 || dtype < 0 || dtype > 1 || (ept != 1 && ept != 2 && ept != 4) ||
+        blocks_per_cu < 0 || blocks_per_cu > 64 || prefetch < 1 || prefetch > 2)
+        return TF_EINVAL;
+    LaunchCfg& c = fn < 4 ? g_cfg[fn][dtype] : g_cfg1[fn - 4][dtype];
+    c.ept = ept;
+    c.bpc = blocks_per_cu;
+    c.pd = prefetch;
+    return TF_OK;
+}
+
+tf_status tf_get_launch_config(int fn, int dtype, int* ept, int* blocks_per_cu, int* prefetch) {
+    if (fn < 0 || fn > 7 || dtype < 0 || dtype > 1 || !ept || !blocks_per_cu || !prefetch)
+        return TF_EINVAL;
+    LaunchCfg c = fn < 4 ? g_cfg[fn][dtype] : g_cfg1[fn - 4][dtype];
+    *ept = c.ept;
+    *blocks_per_cu = c.bpc;
+    *prefetch = c.pd;
+    return TF_OK;
+}
 
 const char* tf_status_string(tf_status s) {
     switch (s) {

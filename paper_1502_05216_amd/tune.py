@@ -1,0 +1,134 @@
+"""Autotuner of the launch configuration (elements per thread, workgroups per
+compute unit) of every kernel, timed with HIP events on the device.
+
+    python -m paper_1502_05216_amd.tune [--n 67108864] [--out PATH]
+
+For each function and format it times every candidate on seeded inputs of the
+benchmark distribution (at a size well beyond the last-level cache, so that
+HBM rather than cache bandwidth is measured), keeps the fastest, and writes a JSON cache keyed by
+the device (name, compute units) and the library version.  `apply()` loads the
+cache for the current device and sets the configuration in the library; the
+package calls it on first use of a kernel.  Without a cache the library's
+built-in defaults apply.
+"""
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+from . import _lib
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+EPTS = (1, 2, 4)
+BPCS = (0, 2, 3, 4, 6, 8)
+PDS = (1, 2)
+
+
+def device_key():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return "%s|%d|%s" % (getattr(p, "gcnArchName", p.name), p.multi_processor_count,
+                         _lib.lib().tf_version().decode())
+
+
+def _time(fn, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(n=1 << 26, reps=10, funcs=None, dtypes=("f64", "f32"), verbose=True):
+    """Time all candidates; return {key: {"fn|dtype": [ept, bpc, pd, ms]}}."""
+    import torch
+    from . import workloads
+    dev = torch.device("cuda:0")
+    res = {}
+    for dts in dtypes:
+        dt = np.float64 if dts == "f64" else np.float32
+        for fn in funcs or (_lib.TWOFOLD + _lib.ONEX):
+            base = {"exp1x": "texp", "expm1_1x": "texpm1", "log1x": "tlog",
+                    "log1p_1x": "tlog1p"}.get(fn, fn)
+            a, b = workloads.twofold_inputs(base, n, dt)
+            x0 = torch.from_numpy(a).to(dev)
+            x1 = torch.from_numpy(b).to(dev)
+            z0 = torch.empty_like(x0)
+            z1 = torch.empty_like(x0)
+            if fn in _lib.TWOFOLD:
+                call = lambda: _lib.twofold_call(fn, x0, x1, out=(z0, z1))
+            else:
+                call = lambda: _lib.onex_call(fn, x0, out=z0)
+            old = _lib.get_launch_config(fn, dts)
+            best = None
+            for ept in EPTS:
+                for bpc in BPCS:
+                    for pd in (PDS if fn in _lib.TWOFOLD else (1,)):
+                        _lib.set_launch_config(fn, dts, ept, bpc, pd)
+                        ms = _time(call, reps)
+                        if verbose:
+                            print("tune %-9s %s ept=%d bpc=%d pd=%d %.4f ms"
+                                  % (fn, dts, ept, bpc, pd, ms), flush=True)
+                        if best is None or ms < best[3]:
+                            best = (ept, bpc, pd, ms)
+            _lib.set_launch_config(fn, dts, *old)
+            res["%s|%s" % (fn, dts)] = list(best)
+            if verbose:
+                print("best %-9s %s ept=%d bpc=%d pd=%d %.4f ms" % ((fn, dts) + best), flush=True)
+            del x0, x1, z0, z1
+    return {device_key(): res}
+
+
+def save(result, path=CACHE):
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data.update(result)
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
+_applied = False
+
+
+def apply(path=CACHE):
+    """Set the tuned configuration for the current device, if the cache has it."""
+    global _applied
+    if _applied:
+        return True
+    _applied = True
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(device_key())
+    if not rec:
+        return False
+    for key, (ept, bpc, pd, _) in rec.items():
+        fn, dts = key.split("|")
+        _lib.set_launch_config(fn, dts, int(ept), int(bpc), int(pd))
+    return True
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=1 << 26)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    r = tune(n=args.n, reps=args.reps)
+    save(r, args.out)
+    print(json.dumps(r, indent=1))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
