@@ -91,6 +91,35 @@ tf_status tf_expm1_1xf(const float* x, float* z, size_t n, void* stream);
 tf_status tf_log1xf(const float* x, float* z, size_t n, void* stream);
 tf_status tf_log1p_1xf(const float* x, float* z, size_t n, void* stream);
 
+/* --- backward (twofold adjoints; not part of the paper) ----------------
+ * Gradient of a twofold function with respect to its twofold argument
+ * x = x0 + x1, given the twofold upstream gradient g = g0 + g1 and the saved
+ * forward value s = s0 + s1:
+ *   tf_texp_bwd    gx = g * z          (s = z = texp(x))
+ *   tf_texpm1_bwd  gx = g * (z + 1)    (s = z = texpm1(x))
+ *   tf_tlog_bwd    gx = g / y          (s = y, the argument of tlog)
+ *   tf_tlog1p_bwd  gx = g / (1 + y)    (s = y, the argument of tlog1p)
+ * in twofold arithmetic: gx0 is the 1x product/quotient of the main parts,
+ * gx1 its correction (division: Dekker's quotient with the FMA remainder
+ * fma(-q, b, a) of the section "Older CPUs").  All six arrays have n elements;
+ * same conventions as above (gx may alias s or g element for element). */
+tf_status tf_texp_bwd(const double* s0, const double* s1, const double* g0, const double* g1, double* gx0,
+                      double* gx1, size_t n, void* stream);
+tf_status tf_texpm1_bwd(const double* s0, const double* s1, const double* g0, const double* g1, double* gx0,
+                        double* gx1, size_t n, void* stream);
+tf_status tf_tlog_bwd(const double* s0, const double* s1, const double* g0, const double* g1, double* gx0,
+                      double* gx1, size_t n, void* stream);
+tf_status tf_tlog1p_bwd(const double* s0, const double* s1, const double* g0, const double* g1, double* gx0,
+                        double* gx1, size_t n, void* stream);
+tf_status tf_texpf_bwd(const float* s0, const float* s1, const float* g0, const float* g1, float* gx0,
+                       float* gx1, size_t n, void* stream);
+tf_status tf_texpm1f_bwd(const float* s0, const float* s1, const float* g0, const float* g1, float* gx0,
+                         float* gx1, size_t n, void* stream);
+tf_status tf_tlogf_bwd(const float* s0, const float* s1, const float* g0, const float* g1, float* gx0,
+                       float* gx1, size_t n, void* stream);
+tf_status tf_tlog1pf_bwd(const float* s0, const float* s1, const float* g0, const float* g1, float* gx0,
+                         float* gx1, size_t n, void* stream);
+
 /* --- launch configuration (used by the autotuner) ----------------------
  * fn: 0 texp, 1 texpm1, 2 tlog, 3 tlog1p, 4 exp1x, 5 expm1_1x, 6 log1x,
  * 7 log1p_1x; dtype: 0 binary64, 1 binary32.  ept: elements per thread

@@ -8,13 +8,15 @@ GPU, in binary64 and binary32:
     z0, z1 = tlog(x0, x1)      # log
     z0, z1 = tlog1p(x0, x1)    # log1p
     z = exp1x(x), expm1_1x(x), log1x(x), log1p_1x(x)   # the 1x main parts
+    gx0, gx1 = texp_bwd(z0, z1, g0, g1)                 # twofold adjoints
+    autograd.TExp / TExpm1 / TLog / TLog1p              # torch.autograd.Function
 
 Arguments are contiguous torch tensors on the GPU; work is enqueued on the
 current stream.  The kernels live in libtwofold_hip.so (csrc/, C ABI in
 include/twofold_hip.h); this package only marshals arguments.
 """
-from ._lib import (ONEX, TWOFOLD, TwofoldError, declared_functions, lib, onex_call,
-                   twofold_call)
+from ._lib import (ONEX, TWOFOLD, TwofoldError, backward_call, declared_functions, lib,
+                   onex_call, twofold_call)
 
 
 def texp(x0, x1, out=None):
@@ -49,10 +51,27 @@ def log1p_1x(x, out=None):
     return onex_call("log1p_1x", x, out)
 
 
+def texp_bwd(s0, s1, g0, g1, out=None):
+    return backward_call("texp", s0, s1, g0, g1, out)
+
+
+def texpm1_bwd(s0, s1, g0, g1, out=None):
+    return backward_call("texpm1", s0, s1, g0, g1, out)
+
+
+def tlog_bwd(s0, s1, g0, g1, out=None):
+    return backward_call("tlog", s0, s1, g0, g1, out)
+
+
+def tlog1p_bwd(s0, s1, g0, g1, out=None):
+    return backward_call("tlog1p", s0, s1, g0, g1, out)
+
+
 def build(verbose=False):
     from . import _build
     return _build.build(verbose=verbose)
 
 
 __all__ = ["texp", "texpm1", "tlog", "tlog1p", "exp1x", "expm1_1x", "log1x", "log1p_1x",
+           "texp_bwd", "texpm1_bwd", "tlog_bwd", "tlog1p_bwd",
            "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX"]

@@ -48,6 +48,11 @@ def _load():
             fn = getattr(lib, "tf_" + f + sfx)
             fn.argtypes = [P, P, S, P]
             fn.restype = ctypes.c_int
+    for f in TWOFOLD:
+        for sfx in ("", "f"):
+            fn = getattr(lib, "tf_" + f + sfx + "_bwd")
+            fn.argtypes = [P, P, P, P, P, P, S, P]
+            fn.restype = ctypes.c_int
     lib.tf_set_launch_config.argtypes = [ctypes.c_int] * 5
     lib.tf_set_launch_config.restype = ctypes.c_int
     lib.tf_get_launch_config.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
@@ -132,6 +137,27 @@ def onex_call(name, x, out=None):
     with torch.cuda.device(x.device):
         _check(fn(x.data_ptr(), z.data_ptr(), x.numel(), _stream()), "tf_" + name)
     return z
+
+
+def backward_call(name, s0, s1, g0, g1, out=None):
+    """Twofold gradient (gx0, gx1) of `name` at the saved forward value
+    (s0, s1) for the twofold upstream gradient (g0, g1): texp g*z,
+    texpm1 g*(z+1), tlog g/y, tlog1p g/(1+y)."""
+    import torch
+    if name not in TWOFOLD:
+        raise ValueError(name)
+    _validate(s0, s1, g0, g1)
+    if out is None:
+        gx0 = torch.empty_like(s0)
+        gx1 = torch.empty_like(s0)
+    else:
+        gx0, gx1 = out
+        _validate(s0, gx0, gx1)
+    fn = getattr(_load(), "tf_" + name + _suffix(s0) + "_bwd")
+    with torch.cuda.device(s0.device):
+        _check(fn(s0.data_ptr(), s1.data_ptr(), g0.data_ptr(), g1.data_ptr(), gx0.data_ptr(),
+                  gx1.data_ptr(), s0.numel(), _stream()), "tf_" + name + "_bwd")
+    return gx0, gx1
 
 
 FN_IDS = {name: i for i, name in enumerate(TWOFOLD + ONEX)}

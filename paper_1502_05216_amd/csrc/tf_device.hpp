@@ -568,4 +568,18 @@ __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> 
     }
 }
 
+// ----------------------------------------------------------------------------
+// Backward: twofold adjoints of the four functions.  With x = x0 + x1, the
+// saved forward value s (z for texp/texpm1, the argument y for tlog/tlog1p)
+// and the twofold upstream gradient g, the gradient with respect to x is
+//   texp g z,  texpm1 g (z + 1),  tlog g / y,  tlog1p g / (1 + y),
+// each evaluated in twofold arithmetic.
+// ----------------------------------------------------------------------------
+template <int FN, class T> __device__ __forceinline__ Tw<T> bwd_elem(Tw<T> s, Tw<T> g) {
+    if constexpr (FN == 0) return mul_tt(g, s);
+    else if constexpr (FN == 1) return mul_tt(g, add_td(s, T(1)));
+    else if constexpr (FN == 2) return div_tt(g, s);
+    else return div_tt(g, add_td(s, T(1)));
+}
+
 }  // namespace tfh

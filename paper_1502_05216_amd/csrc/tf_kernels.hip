@@ -510,6 +510,67 @@ tf_status launch_onex(const T* x, T* z, size_t n, void* stream) {
     }
 }
 
+// Backward kernel: streams s0, s1, g0, g1 -> gx0, gx1 (48 B per binary64
+// element), grid-stride over tiles of kBlock*EPT elements.
+template <class T, int FN, int EPT>
+__global__ __launch_bounds__(kBlock) void k_backward(const T* s0, const T* s1, const T* g0,
+                                                     const T* g1, T* gx0, T* gx1, size_t n) {
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t nfull = n / TILE;
+    const size_t off = (size_t)threadIdx.x * EPT;
+    for (size_t t = blockIdx.x; t < nfull; t += gridDim.x) {
+        const size_t base = t * TILE + off;
+        Vec<T, EPT> a, b, c, d, r0, r1;
+        vload(a, s0 + base);
+        vload(b, s1 + base);
+        vload(c, g0 + base);
+        vload(d, g1 + base);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            Tw<T> r = bwd_elem<FN>(Tw<T>{a.v[e], b.v[e]}, Tw<T>{c.v[e], d.v[e]});
+            r0.v[e] = r.x0;
+            r1.v[e] = r.x1;
+        }
+        vstore(gx0 + base, r0);
+        vstore(gx1 + base, r1);
+    }
+    const size_t rbase = nfull * TILE;
+    if (rbase < n && blockIdx.x == nfull % gridDim.x) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const size_t i = rbase + off + e;
+            if (i < n) {
+                Tw<T> r = bwd_elem<FN>(Tw<T>{s0[i], s1[i]}, Tw<T>{g0[i], g1[i]});
+                gx0[i] = r.x0;
+                gx1[i] = r.x1;
+            }
+        }
+    }
+}
+
+template <class T, int FN>
+tf_status launch_backward(const T* s0, const T* s1, const T* g0, const T* g1, T* gx0, T* gx1,
+                          size_t n, void* stream) {
+    if (n == 0) return TF_OK;
+    if (!s0 || !s1 || !g0 || !g1 || !gx0 || !gx1) return TF_EINVAL;
+    int cus = 0;
+    tf_status st = device_cus(&cus);
+    if (st != TF_OK) return st;
+    const bool al = aligned16(s0) && aligned16(s1) && aligned16(g0) && aligned16(g1) &&
+                    aligned16(gx0) && aligned16(gx1);
+    constexpr int EPT = 16 / sizeof(T);
+    const size_t tile = (size_t)kBlock * (al ? EPT : 1);
+    size_t tiles = n / tile, cap = (size_t)cus * 4;
+    unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
+    if (al)
+        hipLaunchKernelGGL((k_backward<T, FN, EPT>), dim3(grid), dim3(kBlock), 0,
+                           (hipStream_t)stream, s0, s1, g0, g1, gx0, gx1, n);
+    else
+        hipLaunchKernelGGL((k_backward<T, FN, 1>), dim3(grid), dim3(kBlock), 0,
+                           (hipStream_t)stream, s0, s1, g0, g1, gx0, gx1, n);
+    return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
+}
+
 }  // namespace
 
 extern "C" {
@@ -541,6 +602,21 @@ TF_ONEX_ENTRY(tf_exp1xf, float, F1_EXP)
 TF_ONEX_ENTRY(tf_expm1_1xf, float, F1_EXPM1)
 TF_ONEX_ENTRY(tf_log1xf, float, F1_LOG)
 TF_ONEX_ENTRY(tf_log1p_1xf, float, F1_LOG1P)
+
+#define TF_BWD_ENTRY(NAME, T, FN)                                                            \
+    tf_status NAME(const T* s0, const T* s1, const T* g0, const T* g1, T* gx0, T* gx1,       \
+                   size_t n, void* stream) {                                                 \
+        return launch_backward<T, FN>(s0, s1, g0, g1, gx0, gx1, n, stream);                  \
+    }
+
+TF_BWD_ENTRY(tf_texp_bwd, double, 0)
+TF_BWD_ENTRY(tf_texpm1_bwd, double, 1)
+TF_BWD_ENTRY(tf_tlog_bwd, double, 2)
+TF_BWD_ENTRY(tf_tlog1p_bwd, double, 3)
+TF_BWD_ENTRY(tf_texpf_bwd, float, 0)
+TF_BWD_ENTRY(tf_texpm1f_bwd, float, 1)
+TF_BWD_ENTRY(tf_tlogf_bwd, float, 2)
+TF_BWD_ENTRY(tf_tlog1pf_bwd, float, 3)
 
 tf_status tf_set_launch_config(int fn, int dtype, int ept, int blocks_per_cu, int prefetch) {
     if (fn < 0 || fn > 7 || dtype < 0 || dtype > 1 || (ept != 1 && ept != 2 && ept != 4) ||
