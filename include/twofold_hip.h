@@ -120,6 +120,44 @@ tf_status tf_tlogf_bwd(const float* s0, const float* s1, const float* g0, const 
 tf_status tf_tlog1pf_bwd(const float* s0, const float* s1, const float* g0, const float* g1, float* gx0,
                          float* gx1, size_t n, void* stream);
 
+/* --- batched ragged launch --------------------------------------------
+ * Many arrays of uneven lengths, each with its own function and format, in
+ * one persistent launch captured once into a hipGraph.  The plan copies the
+ * descriptors (host memory, read during tf_batch_plan_create only), cuts every
+ * array into chunks of chunk_tiles * 256 * ept elements ordered dearest first,
+ * and owns a small device allocation (descriptors, chunk list, a work
+ * counter) until tf_batch_plan_destroy.  Results equal the plain calls bit
+ * for bit.  Errors: TF_EINVAL for a bad descriptor (func or dtype out of
+ * range, NULL array with n > 0) or configuration, TF_ENOMEM when the device
+ * allocation fails, TF_ELAUNCH when capture fails.  A plan must not be
+ * launched on two streams at once (it owns one work counter); launches on
+ * one stream run in order.  Arrays need not be 16-byte aligned (unaligned
+ * ones take a slower element-wise path). */
+typedef struct {
+    int32_t func;       /* 0 texp, 1 texpm1, 2 tlog, 3 tlog1p */
+    int32_t dtype;      /* 0 binary64, 1 binary32 */
+    size_t n;           /* elements (0 allowed) */
+    const void* x0;     /* device arrays of n elements of the dtype */
+    const void* x1;
+    void* z0;
+    void* z1;
+} tf_batch_desc;
+
+typedef struct {
+    int32_t ept64;          /* elements per thread, binary64 arrays: 1, 2 or 4 */
+    int32_t ept32;          /* binary32 arrays: 2 (with ept64 1) or 4 */
+    int32_t chunk_tiles;    /* tiles of 256*ept elements per chunk, 1..4096 */
+    int32_t blocks_per_cu;  /* workgroups per compute unit, 0 = all resident */
+} tf_batch_config;          /* NULL in tf_batch_plan_create = {2, 4, 8, 0} */
+
+typedef struct tf_batch_plan tf_batch_plan;
+
+tf_status tf_batch_plan_create(const tf_batch_desc* descs, size_t count,
+                               const tf_batch_config* config, tf_batch_plan** plan);
+tf_status tf_batch_launch(tf_batch_plan* plan, void* stream);
+tf_status tf_batch_plan_destroy(tf_batch_plan* plan);
+tf_status tf_batch_plan_info(const tf_batch_plan* plan, size_t* chunks, size_t* elements);
+
 /* --- launch configuration (used by the autotuner) ----------------------
  * fn: 0 texp, 1 texpm1, 2 tlog, 3 tlog1p, 4 exp1x, 5 expm1_1x, 6 log1x,
  * 7 log1p_1x; dtype: 0 binary64, 1 binary32.  ept: elements per thread

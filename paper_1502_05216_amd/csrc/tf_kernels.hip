@@ -12,9 +12,12 @@
 // (|x0| > ln 2), which runs only on waves that hold such a lane.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstdio>
+#include <new>
+#include <vector>
 
 #include "../../include/twofold_hip.h"
 #include "tf_device.hpp"
@@ -187,22 +190,25 @@ __device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, co
     return false;
 }
 
-// Per-wave queue of deferred elements (texpm1 with |x0| > ln 2): the element
-// index and its two argument parts in LDS, appended with a ballot prefix count
-// and drained 64 at a time with one element per lane, so pexp0 runs on full
-// waves and the drain reads no global memory.
-template <class T, int CAP> struct WaveQueue {
-    size_t* qi;   // this wave's slots: index, x0, x1
+// Per-wave queue of deferred elements (texpm1 with |x0| > ln 2): the
+// destination of z1 and the two argument parts, in LDS, appended with a ballot
+// prefix count and drained 64 at a time with one element per lane, so pexp0
+// runs on full waves and the drain reads no global memory.  Entries carry
+// their destination pointer, so one queue serves any array.  CAP = 128: the
+// caller drains after every push that brings n to 64 or more.
+template <class T> struct WaveQueue {
+    static constexpr int CAP = 128;
+    T** qd;       // this wave's slots: z1 destination, x0, x1
     T* qa;
     T* qb;
     int n;        // entries in use (wave-uniform)
 
-    __device__ void push(bool on, size_t idx, T a, T b) {
+    __device__ void push(bool on, T* dst, T a, T b) {
         const unsigned long long m = __ballot(on);
         const int lane_off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
         if (on) {
-            qi[n + lane_off] = idx;
+            qd[n + lane_off] = dst;
             qa[n + lane_off] = a;
             qb[n + lane_off] = b;
         }
@@ -212,21 +218,18 @@ template <class T, int CAP> struct WaveQueue {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // Takes min(n, 64) entries: lane l gets entry l (valid if l < taken).
-    __device__ int pop64(int lane, size_t* idx, T* a, T* b) {
+    __device__ int pop64(int lane, T** dst, T* a, T* b) {
         const int taken = n < 64 ? n : 64;
         if (lane < taken) {
-            *idx = qi[lane];
+            *dst = qd[lane];
             *a = qa[lane];
             *b = qb[lane];
         }
-#pragma unroll
-        for (int k = 1; k * 64 < CAP; ++k) {
-            const int src = k * 64 + lane;
-            if (src < n) {
-                qi[src - 64] = qi[src];
-                qa[src - 64] = qa[src];
-                qb[src - 64] = qb[src];
-            }
+        const int src = 64 + lane;
+        if (src < n) {
+            qd[lane] = qd[src];
+            qa[lane] = qa[src];
+            qb[lane] = qb[src];
         }
         n -= taken;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -236,48 +239,48 @@ template <class T, int CAP> struct WaveQueue {
     }
 };
 
+// LDS slots of the four per-wave queues of a workgroup (sized for binary64,
+// reused as binary32).
+struct QueueSlots {
+    unsigned char raw[kBlock / 64][WaveQueue<double>::CAP * (sizeof(void*) + 2 * sizeof(double))];
+};
+
+template <class T> __device__ __forceinline__ WaveQueue<T> wave_queue(QueueSlots& qs) {
+    constexpr int C = WaveQueue<T>::CAP;
+    unsigned char* base = qs.raw[threadIdx.x / 64];
+    return {reinterpret_cast<T**>(base), reinterpret_cast<T*>(base + C * sizeof(void*)),
+            reinterpret_cast<T*>(base + C * (sizeof(void*) + sizeof(T))), 0};
+}
+
 // Drains up to 64 deferred texpm1 elements with the general form; their z0
 // was already stored by the fast pass, only z1 is written here.
-template <class T, class L, int CAP>
-__device__ __forceinline__ void drain_texpm1(const L& lds, WaveQueue<T, CAP>& wq, int lane,
-                                             T* z1) {
-    size_t i = 0;
+template <class T, class L>
+__device__ __forceinline__ void drain_texpm1(const L& lds, WaveQueue<T>& wq, int lane) {
+    T* dst = nullptr;
     T a = T(1), b = T(0);
-    const int taken = wq.pop64(lane, &i, &a, &b);
+    const int taken = wq.pop64(lane, &dst, &a, &b);
     if (lane < taken) {
         const bool tiny = __all(fabs_(b) < P<T>::EXPM1_TINY);
         T r0, r1;
         texpm1_elem(a, b, tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
-        z1[i] = r1;
+        *dst = r1;
     }
 }
 
-// Twofold kernel.  A tile is kBlock*EPT consecutive elements, thread t owning
-// elements t*EPT .. t*EPT+EPT-1 (16-byte loads and stores, each wave touching
-// one contiguous 64*EPT*sizeof(T) span).  Workgroups walk the full tiles with a
-// grid stride and keep the next PD tiles in flight (loaded into registers
-// before the current tile is evaluated), so HBM latency overlaps arithmetic.
-// The ragged remainder (< one tile) is done by one workgroup with per-element
-// guards and the general form.
-template <class T, int FN, int EPT, int PD>
-__global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T* z0, T* z1,
-                                                    size_t n) {
+// Full tiles t = t0, t0 + step, ... < t_end of one array (a tile is kBlock*EPT
+// consecutive elements, thread t owning elements t*EPT .. t*EPT+EPT-1, so loads
+// and stores are 16 bytes per lane and each wave touches one contiguous span).
+// The next PD tiles are kept in flight (loaded into registers before the
+// current tile is evaluated), so HBM latency overlaps arithmetic.  Deferred
+// texpm1 lanes go to the wave queue, which the caller drains at the end.
+template <class T, int FN, int EPT, int PD, class L>
+__device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const T* x0,
+                                          const T* x1, T* z0, T* z1, size_t t0, size_t t_end,
+                                          size_t step) {
     constexpr bool QUEUE = FN == FN_TEXPM1;
-    constexpr int QCAP = 64 + 64 * EPT;   // < 64 left after a drain, + one tile
-    constexpr int QW = QUEUE ? kBlock / 64 : 1, QC = QUEUE ? QCAP : 1;
-    __shared__ typename LdsFor<T, FN>::type lds;
-    __shared__ size_t q_idx[QW][QC];
-    __shared__ T q_x0[QW][QC];
-    __shared__ T q_x1[QW][QC];
-    lds.load();
-    __syncthreads();
     constexpr size_t TILE = (size_t)kBlock * EPT;
-    const size_t nfull = n / TILE;
-    const size_t stride = gridDim.x;
     const size_t off = (size_t)threadIdx.x * EPT;
     const int lane = threadIdx.x & 63;
-    const int w = QUEUE ? threadIdx.x / 64 : 0;
-    WaveQueue<T, QCAP> wq{q_idx[w], q_x0[w], q_x1[w], 0};
     Vec<T, EPT> a[PD + 1], b[PD + 1], r0, r1;
 #pragma unroll
     for (int s = 0; s <= PD; ++s) {
@@ -287,18 +290,17 @@ __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T*
             b[s].v[e] = T(0);
         }
     }
-    size_t t = blockIdx.x;
 #pragma unroll
     for (int s = 0; s < PD; ++s) {
-        const size_t ts = t + (size_t)s * stride;
-        if (ts < nfull) {
+        const size_t ts = t0 + (size_t)s * step;
+        if (ts < t_end) {
             vload(a[s], x0 + ts * TILE + off);
             vload(b[s], x1 + ts * TILE + off);
         }
     }
-    for (; t < nfull; t += stride) {
-        const size_t tn = t + (size_t)PD * stride;
-        if (tn < nfull) {
+    for (size_t t = t0; t < t_end; t += step) {
+        const size_t tn = t + (size_t)PD * step;
+        if (tn < t_end) {
             vload(a[PD], x0 + tn * TILE + off);
             vload(b[PD], x1 + tn * TILE + off);
         }
@@ -312,9 +314,9 @@ __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T*
             for (int e = 0; e < EPT; ++e) {
                 const bool d = (deferred >> e) & 1u;
                 if (!d) z1[base + e] = r1.v[e];
-                wq.push(d, base + e, a[0].v[e], b[0].v[e]);
+                wq.push(d, z1 + base + e, a[0].v[e], b[0].v[e]);
+                if (wq.n >= 64) drain_texpm1<T>(lds, wq, lane);
             }
-            while (wq.n >= 64) drain_texpm1<T>(lds, wq, lane, z1);
         } else {
             vstore(z1 + base, r1);
         }
@@ -324,18 +326,24 @@ __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T*
             b[s] = b[s + 1];
         }
     }
-    if constexpr (QUEUE) {
-        while (wq.n > 0) drain_texpm1<T>(lds, wq, lane, z1);
-    }
-    const size_t rbase = nfull * TILE;
-    if (rbase < n && blockIdx.x == nfull % stride) {
+}
+
+// Elements [base, end) of one array, fewer than one tile's worth per call
+// step: per-element guards and the general form (ragged remainders, and whole
+// arrays that are not 16-byte aligned).
+template <class T, int FN, int EPT, class L>
+__device__ __forceinline__ void run_guarded(const L& lds, const T* x0, const T* x1, T* z0, T* z1,
+                                            size_t base, size_t end) {
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t off = (size_t)threadIdx.x * EPT;
+    for (size_t b0 = base; b0 < end; b0 += TILE) {
+        Vec<T, EPT> ra, rb, r0, r1;
         bool tiny = true;
-        Vec<T, EPT> ra, rb;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            size_t i = rbase + off + e;
-            ra.v[e] = i < n ? x0[i] : pad_arg<T>();
-            rb.v[e] = i < n ? x1[i] : T(0);
+            const size_t i = b0 + off + e;
+            ra.v[e] = i < end ? x0[i] : pad_arg<T>();
+            rb.v[e] = i < end ? x1[i] : T(0);
             tiny = tiny && (fabs_(rb.v[e]) < P<T>::EXPM1_TINY);
         }
         const bool x1_tiny = __all(tiny);
@@ -344,13 +352,155 @@ __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T*
             eval_general<T, FN>(lds, ra.v[e], rb.v[e], x1_tiny, r0.v[e], r1.v[e]);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            size_t i = rbase + off + e;
-            if (i < n) {
+            const size_t i = b0 + off + e;
+            if (i < end) {
                 z0[i] = r0.v[e];
                 z1[i] = r1.v[e];
             }
         }
     }
+}
+
+// Plain twofold kernel over one array: workgroups walk the full tiles with a
+// grid stride; the ragged remainder (< one tile) is done by one workgroup.
+template <class T, int FN, int EPT, int PD>
+__global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T* z0, T* z1,
+                                                    size_t n) {
+    __shared__ typename LdsFor<T, FN>::type lds;
+    __shared__ QueueSlots qs;
+    lds.load();
+    __syncthreads();
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t nfull = n / TILE;
+    WaveQueue<T> wq = wave_queue<T>(qs);
+    run_tiles<T, FN, EPT, PD>(lds, wq, x0, x1, z0, z1, blockIdx.x, nfull, gridDim.x);
+    if constexpr (FN == FN_TEXPM1) {
+        while (wq.n > 0) drain_texpm1<T>(lds, wq, threadIdx.x & 63);
+    }
+    if (nfull * TILE < n && blockIdx.x == nfull % gridDim.x)
+        run_guarded<T, FN, EPT>(lds, x0, x1, z0, z1, nfull * TILE, n);
+}
+
+// ----------------------------------------------------------------------------
+// Batched ragged launch: many arrays of any length, function and format in one
+// persistent launch.  The host cuts every array into chunks of chunk_tiles
+// tiles and orders the chunks by estimated cost (dearest first); workgroups
+// pull chunks from a device counter and run them with the same tile loop as
+// the plain kernels.  The LDS tables are restaged only when the (function,
+// format) of the next chunk differs from the current one; with the cost order
+// that happens a handful of times per workgroup.
+// ----------------------------------------------------------------------------
+struct BatchDesc {       // device copy of one tf_batch_desc
+    int func, dtype, aligned, pad;
+    size_t n;
+    const void* x0;
+    const void* x1;
+    void* z0;
+    void* z1;
+};
+struct BatchChunk {
+    unsigned desc, chunk;
+};
+
+union BatchLds {
+    Lds<double, true, true, false, false> d_exp;
+    Lds<double, true, true, true, false> d_expm1;
+    Lds<double, false, false, true, true> d_log;
+    Lds<float, true, true, false, false> f_exp;
+    Lds<float, true, true, true, false> f_expm1;
+    Lds<float, false, false, true, true> f_log;
+};
+
+__device__ __forceinline__ void batch_stage(BatchLds& lds, int key) {
+    switch (key) {
+        case 0: lds.d_exp.load(); break;
+        case 2: lds.d_expm1.load(); break;
+        case 4: case 6: lds.d_log.load(); break;
+        case 1: lds.f_exp.load(); break;
+        case 3: lds.f_expm1.load(); break;
+        default: lds.f_log.load(); break;
+    }
+}
+
+template <class T, int FN, int EPT, class L>
+__device__ __forceinline__ void batch_chunk(const L& lds, WaveQueue<T>& wq, const BatchDesc& d,
+                                            unsigned chunk, unsigned chunk_tiles) {
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t start = (size_t)chunk * chunk_tiles * TILE;
+    const size_t lim = start + (size_t)chunk_tiles * TILE;
+    const size_t end = lim < d.n ? lim : d.n;
+    const T* x0 = static_cast<const T*>(d.x0);
+    const T* x1 = static_cast<const T*>(d.x1);
+    T* z0 = static_cast<T*>(d.z0);
+    T* z1 = static_cast<T*>(d.z1);
+    size_t g0 = start;
+    if (d.aligned) {
+        const size_t t0 = start / TILE, t1 = end / TILE;
+        run_tiles<T, FN, EPT, 1>(lds, wq, x0, x1, z0, z1, t0, t1, 1);
+        g0 = t1 * TILE;
+    }
+    if (g0 < end) run_guarded<T, FN, EPT>(lds, x0, x1, z0, z1, g0, end);
+}
+
+template <int EPT64, int EPT32>
+__device__ __forceinline__ void batch_dispatch(BatchLds& lds, WaveQueue<double>& q64,
+                                               WaveQueue<float>& q32, const BatchDesc& d,
+                                               int key, unsigned chunk, unsigned ct) {
+    switch (key) {
+        case 0: batch_chunk<double, FN_TEXP, EPT64>(lds.d_exp, q64, d, chunk, ct); break;
+        case 2: batch_chunk<double, FN_TEXPM1, EPT64>(lds.d_expm1, q64, d, chunk, ct); break;
+        case 4: batch_chunk<double, FN_TLOG, EPT64>(lds.d_log, q64, d, chunk, ct); break;
+        case 6: batch_chunk<double, FN_TLOG1P, EPT64>(lds.d_log, q64, d, chunk, ct); break;
+        case 1: batch_chunk<float, FN_TEXP, EPT32>(lds.f_exp, q32, d, chunk, ct); break;
+        case 3: batch_chunk<float, FN_TEXPM1, EPT32>(lds.f_expm1, q32, d, chunk, ct); break;
+        case 5: batch_chunk<float, FN_TLOG, EPT32>(lds.f_log, q32, d, chunk, ct); break;
+        default: batch_chunk<float, FN_TLOG1P, EPT32>(lds.f_log, q32, d, chunk, ct); break;
+    }
+}
+
+// Empties the texpm1 queue of the (function, format) being left.
+__device__ __forceinline__ void batch_drain(BatchLds& lds, WaveQueue<double>& q64,
+                                            WaveQueue<float>& q32, int key) {
+    const int lane = threadIdx.x & 63;
+    if (key == 2) {
+        while (q64.n > 0) drain_texpm1<double>(lds.d_expm1, q64, lane);
+    } else if (key == 3) {
+        while (q32.n > 0) drain_texpm1<float>(lds.f_expm1, q32, lane);
+    }
+}
+
+__global__ void k_batch_reset(unsigned* counter) { *counter = 0u; }
+
+template <int EPT64, int EPT32>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const BatchDesc* descs,
+                                                  const BatchChunk* chunks, unsigned nchunks,
+                                                  unsigned* counter, unsigned chunk_tiles) {
+    __shared__ BatchLds lds;
+    __shared__ QueueSlots qs;
+    __shared__ unsigned s_chunk;
+    WaveQueue<double> q64 = wave_queue<double>(qs);
+    WaveQueue<float> q32 = wave_queue<float>(qs);
+    int cur = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1u);
+        __syncthreads();
+        // uniform across the workgroup: keep it (and the descriptor) scalar
+        const unsigned c = __builtin_amdgcn_readfirstlane(s_chunk);
+        __syncthreads();
+        if (c >= nchunks) break;
+        const BatchChunk ch = chunks[c];
+        const BatchDesc d = descs[ch.desc];
+        const int key = d.func * 2 + d.dtype;
+        if (key != cur) {
+            if (cur >= 0) batch_drain(lds, q64, q32, cur);
+            __syncthreads();
+            batch_stage(lds, key);
+            __syncthreads();
+            cur = key;
+        }
+        batch_dispatch<EPT64, EPT32>(lds, q64, q32, d, key, ch.chunk, chunk_tiles);
+    }
+    if (cur >= 0) batch_drain(lds, q64, q32, cur);
 }
 
 template <class T, int F1>
@@ -571,6 +721,59 @@ tf_status launch_backward(const T* s0, const T* s1, const T* g0, const T* g1, T*
     return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
 }
 
+// Relative cost per element of each (function, format), used to order the
+// chunks of a batch (measured plain-kernel times on 2^26 elements).
+constexpr double kCost[4][2] = {{1.00, 0.46}, {1.25, 0.64}, {1.28, 0.61}, {1.35, 0.60}};
+
+}  // namespace
+
+struct tf_batch_plan {
+    BatchDesc* d_descs = nullptr;
+    BatchChunk* d_chunks = nullptr;
+    unsigned* d_counter = nullptr;
+    unsigned nchunks = 0;
+    size_t elements = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+namespace {
+
+void plan_free(tf_batch_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_descs) (void)hipFree(p->d_descs);
+    if (p->d_chunks) (void)hipFree(p->d_chunks);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    delete p;
+}
+
+template <int E64, int E32>
+tf_status batch_capture(tf_batch_plan* p, int cus, int bpc, unsigned chunk_tiles) {
+    auto kern = k_batch<E64, E32>;
+    int occ = blocks_per_cu(kern);
+    unsigned grid = (unsigned)cus * (unsigned)(bpc > 0 ? bpc : occ);
+    if (grid > p->nchunks) grid = p->nchunks > 0 ? p->nchunks : 1;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return TF_ELAUNCH;
+    tf_status st = TF_OK;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        st = TF_ELAUNCH;
+    } else {
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, p->d_counter);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, p->d_descs, p->d_chunks,
+                           p->nchunks, p->d_counter, chunk_tiles);
+        if (hipStreamEndCapture(s, &p->graph) != hipSuccess ||
+            hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+            st = TF_ELAUNCH;
+    }
+    (void)hipStreamDestroy(s);
+    (void)hipGetLastError();
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -636,6 +839,100 @@ tf_status tf_get_launch_config(int fn, int dtype, int* ept, int* blocks_per_cu, 
     *ept = c.ept;
     *blocks_per_cu = c.bpc;
     *prefetch = c.pd;
+    return TF_OK;
+}
+
+tf_status tf_batch_plan_create(const tf_batch_desc* descs, size_t count,
+                               const tf_batch_config* config, tf_batch_plan** out) {
+    if (!out || (count > 0 && !descs)) return TF_EINVAL;
+    *out = nullptr;
+    tf_batch_config c = {2, 4, 8, 0};
+    if (config) c = *config;
+    if (!((c.ept64 == 2 && c.ept32 == 4) || (c.ept64 == 4 && c.ept32 == 4) ||
+          (c.ept64 == 1 && c.ept32 == 2)) ||
+        c.chunk_tiles < 1 || c.chunk_tiles > 4096 || c.blocks_per_cu < 0 || c.blocks_per_cu > 64)
+        return TF_EINVAL;
+    if (count > 0xffffffffu) return TF_EINVAL;
+    for (size_t i = 0; i < count; ++i) {
+        const tf_batch_desc& d = descs[i];
+        if (d.func < 0 || d.func > 3 || d.dtype < 0 || d.dtype > 1) return TF_EINVAL;
+        if (d.n > 0 && (!d.x0 || !d.x1 || !d.z0 || !d.z1)) return TF_EINVAL;
+    }
+    int cus = 0;
+    tf_status st = device_cus(&cus);
+    if (st != TF_OK) return st;
+    std::vector<BatchDesc> hd(count);
+    struct Item { double cost; BatchChunk ch; };
+    std::vector<Item> items;
+    size_t total = 0;
+    for (size_t i = 0; i < count; ++i) {
+        const tf_batch_desc& d = descs[i];
+        const bool al = aligned16(d.x0) && aligned16(d.x1) && aligned16(d.z0) && aligned16(d.z1);
+        hd[i] = BatchDesc{d.func, d.dtype, al ? 1 : 0, 0, d.n, d.x0, d.x1, d.z0, d.z1};
+        const size_t chunk = (size_t)c.chunk_tiles * kBlock * (d.dtype == 0 ? c.ept64 : c.ept32);
+        const size_t nch = (d.n + chunk - 1) / chunk;
+        if (nch > 0xffffffffull) return TF_EINVAL;
+        for (size_t k = 0; k < nch; ++k) {
+            const size_t len = (k + 1 < nch) ? chunk : d.n - k * chunk;
+            items.push_back({(double)len * kCost[d.func][d.dtype], {(unsigned)i, (unsigned)k}});
+        }
+        total += d.n;
+    }
+    if (items.size() > 0xffffffffull) return TF_EINVAL;
+    // dearest chunks first; equal costs keep descriptor order
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    std::vector<BatchChunk> hc(items.size());
+    for (size_t k = 0; k < items.size(); ++k) hc[k] = items[k].ch;
+
+    tf_batch_plan* p = new (std::nothrow) tf_batch_plan();
+    if (!p) return TF_ENOMEM;
+    p->nchunks = (unsigned)hc.size();
+    p->elements = total;
+    (void)hipGetDevice(&p->device);
+    const size_t dbytes = hd.size() * sizeof(BatchDesc), cbytes = hc.size() * sizeof(BatchChunk);
+    if (hipMalloc(&p->d_descs, dbytes > 0 ? dbytes : 16) != hipSuccess ||
+        hipMalloc(&p->d_chunks, cbytes > 0 ? cbytes : 16) != hipSuccess ||
+        hipMalloc(&p->d_counter, sizeof(unsigned)) != hipSuccess) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return TF_ENOMEM;
+    }
+    if ((dbytes && hipMemcpy(p->d_descs, hd.data(), dbytes, hipMemcpyHostToDevice) != hipSuccess) ||
+        (cbytes && hipMemcpy(p->d_chunks, hc.data(), cbytes, hipMemcpyHostToDevice) != hipSuccess)) {
+        (void)hipGetLastError();
+        plan_free(p);
+        return TF_ELAUNCH;
+    }
+    if (p->nchunks > 0) {
+        if (c.ept64 == 2) st = batch_capture<2, 4>(p, cus, c.blocks_per_cu, c.chunk_tiles);
+        else if (c.ept64 == 4) st = batch_capture<4, 4>(p, cus, c.blocks_per_cu, c.chunk_tiles);
+        else st = batch_capture<1, 2>(p, cus, c.blocks_per_cu, c.chunk_tiles);
+        if (st != TF_OK) {
+            plan_free(p);
+            return st;
+        }
+    }
+    *out = p;
+    return TF_OK;
+}
+
+tf_status tf_batch_launch(tf_batch_plan* plan, void* stream) {
+    if (!plan) return TF_EINVAL;
+    if (plan->nchunks == 0) return TF_OK;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? TF_OK : TF_ELAUNCH;
+}
+
+tf_status tf_batch_plan_destroy(tf_batch_plan* plan) {
+    if (!plan) return TF_EINVAL;
+    plan_free(plan);
+    return TF_OK;
+}
+
+tf_status tf_batch_plan_info(const tf_batch_plan* plan, size_t* chunks, size_t* elements) {
+    if (!plan) return TF_EINVAL;
+    if (chunks) *chunks = plan->nchunks;
+    if (elements) *elements = plan->elements;
     return TF_OK;
 }
 

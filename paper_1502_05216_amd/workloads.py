@@ -148,3 +148,25 @@ def chain_inputs(n, seed=SEED + 4, dtype=np.float64):
     g0 = rng.uniform(-1.0, 1.0, n).astype(dt)
     g1 = ((g0 * rng.uniform(-1.0, 1.0, n).astype(dt)) * _eps(dt)).astype(dt)
     return x0, x1, g0, g1
+
+
+def batch_inputs(descs, seed=SEED + 5, edges=0.001, align=16):
+    """Inputs for a ragged batch: for each (func, dtype) one pool drawn with
+    twofold_inputs over the total length, cut into the batch's arrays in
+    order, each array starting on an `align`-byte boundary of the pool.
+    Returns a list of (func, dtype, x0, x1) numpy views (pool slices)."""
+    out = [None] * len(descs)
+    groups = {}
+    for i, (fn, dt, n) in enumerate(descs):
+        groups.setdefault((fn, np.dtype(dt).type), []).append(i)
+    for k, ((fn, dt), idx) in enumerate(sorted(groups.items(), key=lambda t: (t[0][0], str(t[0][1])))):
+        step = max(1, align // np.dtype(dt).itemsize)
+        offs, pos = [], 0
+        for i in idx:
+            offs.append(pos)
+            pos += -(-descs[i][2] // step) * step
+        x0, x1 = twofold_inputs(fn, max(pos, 1), dt, seed=seed + 17 * k, edges=edges)
+        for i, o in zip(idx, offs):
+            n = descs[i][2]
+            out[i] = (fn, dt, x0[o:o + n], x1[o:o + n])
+    return out

@@ -101,3 +101,28 @@ def test_gpu_tables_equal_oracle_tables(f):
         assert h(k) == o(k), k
     for k in ("L", "K", "N", "N1", "E_OFF", "E_CNT", "C_OFF", "C_CNT", "CM1_OFF", "CM1_CNT"):
         assert h(k) == o(k), k
+
+
+def test_batch_plan_validation(lib):
+    """Descriptor and configuration checks run before any HIP call."""
+    from paper_1502_05216_amd import batch
+    L = batch._bind(lib)
+    P = ctypes.c_void_p
+    out = P()
+    fake = 0x1000
+    good = batch.BatchDesc(0, 0, 10, fake, fake, fake, fake)
+    arr = (batch.BatchDesc * 1)(good)
+    cfg = batch.BatchConfig(2, 4, 8, 0)
+    for d in (batch.BatchDesc(4, 0, 10, fake, fake, fake, fake),      # func out of range
+              batch.BatchDesc(0, 2, 10, fake, fake, fake, fake),      # dtype out of range
+              batch.BatchDesc(1, 1, 10, fake, None, fake, fake)):     # NULL array, n > 0
+        bad = (batch.BatchDesc * 1)(d)
+        assert L.tf_batch_plan_create(bad, 1, ctypes.byref(cfg), ctypes.byref(out)) == 1
+    for c in ((3, 4, 8, 0), (2, 4, 0, 0), (2, 4, 8, -1), (2, 2, 8, 0)):
+        bc = batch.BatchConfig(*c)
+        assert L.tf_batch_plan_create(arr, 1, ctypes.byref(bc), ctypes.byref(out)) == 1
+    assert L.tf_batch_plan_create(None, 1, ctypes.byref(cfg), ctypes.byref(out)) == 1
+    assert L.tf_batch_plan_create(arr, 1, ctypes.byref(cfg), None) == 1
+    assert L.tf_batch_launch(None, None) == 1
+    assert L.tf_batch_plan_destroy(None) == 1
+    assert L.tf_batch_plan_info(None, None, None) == 1
