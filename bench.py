@@ -6,15 +6,18 @@ in HBM, seeded synthetic data of the paper's random-sample kind, 0.1% edge
 arguments).  value = elements per second over the whole step (Gelem/s).
 
 Printed as one JSON line on stdout; progress goes to stderr.  Extra fields:
-per-function binary64 and binary32 rates from HIP events on the launch stream,
+per-function binary64 and binary32 rates from HIP events on the launch stream;
 the roofline of the dominant kernel (algorithmic FP64 flops from the oracle's
-counting build, tests/golden/opcounts.json, over the measured kernel time),
-and the CPU oracle timed on the host cores on a bounded sample.
+counting build, tests/golden/opcounts.json, over the measured kernel time);
+the batched launch over 4096 ragged arrays of mixed function and format
+against the per-array launches and the mix-weighted plain rate; the forward
+and backward chain tlog1p(texpm1(texp(x))) at 2^24; and the CPU oracle timed
+on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f32]
+                    [--no-batch] [--no-chain]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -38,26 +41,29 @@ def log(*a):
 
 
 def src_hash():
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1502_05216_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1502_05216_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1502_05216_amd._build import source_hash
+    return source_hash()
 
 
-def kernel_ms(fn, args, reps):
-    """Average duration of one launch, HIP events on the launch stream."""
+def kernel_ms(fn, args, reps, warm=5, windows=2):
+    """Duration of one launch: HIP events on the launch stream around `reps`
+    back-to-back launches after `warm` untimed ones; the faster of `windows`
+    such windows (the first can still see the clock ramp up)."""
     import torch
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    fn(*args)
-    e0.record(st)
-    for _ in range(reps):
+    for _ in range(warm):
         fn(*args)
-    e1.record(st)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps
+    best = float("inf")
+    for _ in range(windows):
+        e0.record(st)
+        for _ in range(reps):
+            fn(*args)
+        e1.record(st)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
+    return best
 
 
 def traffic_for(kernel, n_elem):
@@ -74,21 +80,103 @@ def traffic_for(kernel, n_elem):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(inputs64, sample):
+PAPER_MOPS_PER_CORE = {"texp": 11.86, "texpm1": 12.28, "tlog": 7.00, "tlog1p": 7.06}
+
+
+def cpu_baseline(inputs64, min_seconds, core_sample):
+    """The oracle on the host: whole passes over the step's binary64 arrays on
+    up to 16 threads until min_seconds have passed, plus a one-thread rate per
+    function on the first core_sample elements (the paper's per-core figure)."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    t = 0.0
+    t, passes = 0.0, 0
+    while passes == 0 or t < min_seconds:
+        for fn in FUNCS:
+            x0, x1 = inputs64[fn]
+            t0 = time.perf_counter()
+            getattr(oracle, fn)(x0, x1, threads=threads)
+            t += time.perf_counter() - t0
+        passes += 1
+        log("cpu baseline: pass %d, %.1f s" % (passes, t))
+    n = inputs64[FUNCS[0]][0].size
+    per_core = {}
     for fn in FUNCS:
-        x0, x1 = inputs64[fn]
-        a0 = np.ascontiguousarray(x0[:sample])
-        a1 = np.ascontiguousarray(x1[:sample])
+        a0 = np.ascontiguousarray(inputs64[fn][0][:core_sample])
+        a1 = np.ascontiguousarray(inputs64[fn][1][:core_sample])
         t0 = time.perf_counter()
-        getattr(oracle, fn)(a0, a1, threads=threads)
-        t += time.perf_counter() - t0
-    return {"value": 4 * sample / t / 1e9, "unit": "Gelem/s", "cores": threads, "kind": "oracle",
-            "sample": "the first %d elements of each of the 4 binary64 benchmark arrays "
-                      "(%d elements), scalar oracle, OpenMP static schedule" % (sample, 4 * sample),
-            "seconds": t}
+        getattr(oracle, fn)(a0, a1, threads=1)
+        per_core[fn] = {"mops": core_sample / (time.perf_counter() - t0) / 1e6,
+                        "paper_mops": PAPER_MOPS_PER_CORE[fn]}
+    return {"value": passes * 4 * n / t / 1e9, "unit": "Gelem/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d whole pass(es) over the step's 4 binary64 arrays of %d elements, "
+                      "scalar oracle, OpenMP static schedule" % (passes, n),
+            "seconds": t, "host_cpus": os.cpu_count(),
+            "one_thread": {"sample": core_sample, "per_function": per_core}}
+
+
+def bench_batch(tf, workloads, per64, per32, reps):
+    """The batched ragged launch over 4096 arrays (function uniform over the
+    four, binary64 with probability 3/4, lengths 2^U[0, 20]) against (i) one
+    plain launch per array and (ii) the plain 2^26 rates weighted by the mix."""
+    import torch
+    from paper_1502_05216_amd.batch import BatchPlan
+    dev = torch.device("cuda:0")
+    descs = workloads.batch_descriptors()
+    host = workloads.batch_inputs(descs)
+    items = []
+    for fn, dt, x0, x1 in host:
+        a0 = torch.from_numpy(np.ascontiguousarray(x0)).to(dev)
+        a1 = torch.from_numpy(np.ascontiguousarray(x1)).to(dev)
+        items.append((fn, a0, a1, torch.empty_like(a0), torch.empty_like(a0)))
+    del host
+    total = sum(it[1].numel() for it in items)
+    with BatchPlan(items) as plan:
+        ms = kernel_ms(plan.launch, (), reps)
+        config = plan.config
+
+    def loop():
+        for fn, a0, a1, z0, z1 in items:
+            getattr(tf, fn)(a0, a1, out=(z0, z1))
+    loop_ms = kernel_ms(loop, (), 2, warm=1, windows=1)
+    mix_ms = None
+    if per32:
+        mix_ms = 0.0
+        for fn, a0, _, _, _ in items:
+            rate = (per64[fn]["windowed_gelem_s"] if a0.dtype == torch.float64
+                    else per32[fn]["gelem_s"])
+            mix_ms += a0.numel() / rate / 1e6
+    del items
+    torch.cuda.empty_cache()
+    return {"arrays": len(descs), "elements": total, "config": list(config), "ms": ms,
+            "gelem_s": total / ms / 1e6, "per_array_launches_ms": loop_ms,
+            "per_array_launches_gelem_s": total / loop_ms / 1e6,
+            "mix_weighted_plain_gelem_s": None if mix_ms is None else total / mix_ms / 1e6,
+            "vs_mix_weighted_plain": None if mix_ms is None else mix_ms / ms}
+
+
+def bench_chain(tf, workloads, reps):
+    """Forward and backward of y = tlog1p(texpm1(texp(x))) on 2^24 binary64
+    twofolds: three forward and three backward launches per pass."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = 1 << 24
+    arrs = [torch.from_numpy(a).to(dev) for a in workloads.chain_inputs(n)]
+    x0, x1, g0, g1 = arrs
+    buf = [torch.empty_like(x0) for _ in range(12)]
+
+    def fwd_bwd():
+        a = tf.texp(x0, x1, out=(buf[0], buf[1]))
+        b = tf.texpm1(*a, out=(buf[2], buf[3]))
+        tf.tlog1p(*b, out=(buf[4], buf[5]))
+        c = tf.tlog1p_bwd(*b, g0, g1, out=(buf[6], buf[7]))
+        d = tf.texpm1_bwd(*b, *c, out=(buf[8], buf[9]))
+        tf.texp_bwd(*a, *d, out=(buf[10], buf[11]))
+    ms = kernel_ms(fwd_bwd, (), reps)
+    del arrs, buf
+    torch.cuda.empty_cache()
+    return {"n": n, "ms": ms, "gelem_s": n / ms / 1e6,
+            "launches": 6, "hbm_bytes_per_elem": 3 * 32 + 3 * 48}
 
 
 def main():
@@ -98,11 +186,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 rates")
-    ap.add_argument("--cpu-sample", type=int, default=N)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched launch")
+    ap.add_argument("--no-chain", action="store_true", help="skip the forward+backward chain")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU oracle time (whole passes over the step)")
+    ap.add_argument("--cpu-core-sample", type=int, default=1 << 21)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the functions are "
-              "elementwise; sharding is by contiguous element ranges, see DESIGN.md)",
+              "elementwise; a multi-GPU run would give each GPU a contiguous element range)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -121,18 +213,28 @@ def main():
     out64 = {fn: (torch.empty_like(a), torch.empty_like(a)) for fn, (a, _) in dev64.items()}
     torch.cuda.synchronize()
 
-    def step():
-        for fn in FUNCS:
+    stream = torch.cuda.current_stream()
+
+    def step(marks=None):
+        # marks: one HIP event before the first launch and one after each
+        # launch, recorded on the stream the kernels run on
+        if marks is not None:
+            marks[0].record(stream)
+        for k, fn in enumerate(FUNCS):
             getattr(tf, fn)(dev64[fn][0], dev64[fn][1], out=out64[fn])
+            if marks is not None:
+                marks[k + 1].record(stream)
 
     log("warmup %d steps" % args.warmup)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log("timing %d steps" % args.steps)
+    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(len(FUNCS) + 1)]
+             for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        step(marks[k])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt / args.steps * 1e3
@@ -141,13 +243,18 @@ def main():
     with open(os.path.join(ROOT, "tests", "golden", "opcounts.json")) as f:
         opc = json.load(f)
 
+    # average launch duration of each kernel over the timed steps
     per64 = {}
-    for fn in FUNCS:
-        ms = kernel_ms(lambda: getattr(tf, fn)(dev64[fn][0], dev64[fn][1], out=out64[fn]), (), 10)
+    for j, fn in enumerate(FUNCS):
+        ms = sum(m[j].elapsed_time(m[j + 1]) for m in marks) / args.steps
         per64[fn] = {"ms": ms, "gelem_s": N / ms / 1e6,
                      "fp64_tflops": N * opc["f64"][fn]["flops"] / ms / 1e9,
                      "hbm_gbs": N * BYTES_PER_ELEM["f64"] / ms / 1e6}
-        log("f64 %-7s %.3f ms  %.1f Gelem/s" % (fn, ms, per64[fn]["gelem_s"]))
+        # the same kernel timed like the binary32 and batched launches below
+        w = kernel_ms(lambda: getattr(tf, fn)(dev64[fn][0], dev64[fn][1], out=out64[fn]), (), 10)
+        per64[fn]["windowed_gelem_s"] = N / w / 1e6
+        log("f64 %-7s %.3f ms  %.1f Gelem/s (windowed %.1f)" % (fn, ms, per64[fn]["gelem_s"],
+                                                              per64[fn]["windowed_gelem_s"]))
     dom = max(FUNCS, key=lambda f: per64[f]["ms"])
     ach = per64[dom]["fp64_tflops"]
     traffic = traffic_for("f64_" + dom, N)
@@ -175,10 +282,24 @@ def main():
             log("f32 %-7s %.3f ms  %.1f Gelem/s" % (fn, ms, per32[fn]["gelem_s"]))
             del x0, x1, o
 
+    batch = None
+    if not args.no_batch:
+        log("batched launch: 4096 ragged arrays")
+        batch = bench_batch(tf, workloads, per64, per32, 10)
+        log("batched %.3f ms  %.1f Gelem/s  (per-array launches %.1f ms, vs mix-weighted plain %s)"
+            % (batch["ms"], batch["gelem_s"], batch["per_array_launches_ms"],
+               batch["vs_mix_weighted_plain"]))
+
+    chain = None
+    if not args.no_chain:
+        log("forward+backward chain, 2^24")
+        chain = bench_chain(tf, workloads, 10)
+        log("chain %.3f ms  %.1f Gelem/s" % (chain["ms"], chain["gelem_s"]))
+
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline: oracle on %d elements per function" % args.cpu_sample)
-        cpu = cpu_baseline(host64, args.cpu_sample)
+        log("cpu baseline: oracle, at least %.0f s" % args.cpu_seconds)
+        cpu = cpu_baseline(host64, args.cpu_seconds, args.cpu_core_sample)
         log("cpu baseline %.4f Gelem/s on %d threads (%.1f s)" % (cpu["value"], cpu["cores"],
                                                                 cpu["seconds"]))
 
@@ -194,6 +315,8 @@ def main():
         "cpu_baseline": cpu,
         "per_function_f64": per64,
         "per_function_f32": per32,
+        "batched": batch,
+        "fwd_bwd_chain": chain,
         "src_hash": src_hash(),
     }
     print(json.dumps(rec), flush=True)

@@ -1,4 +1,5 @@
 """Builds libtwofold_hip.so (HIP, gfx950) in-tree with hipcc."""
+import hashlib
 import os
 import subprocess
 
@@ -47,6 +48,18 @@ def build(verbose=False, extra=()):
         print(out)
     os.replace(tmp, LIB)
     return LIB
+
+
+def source_hash():
+    """Hash of the library's sources (csrc/): ties a measurement to the code it
+    measured."""
+    h = hashlib.sha256()
+    d = os.path.join(PKG, "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".inc", ".py")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 if __name__ == "__main__":

@@ -846,7 +846,7 @@ tf_status tf_batch_plan_create(const tf_batch_desc* descs, size_t count,
                                const tf_batch_config* config, tf_batch_plan** out) {
     if (!out || (count > 0 && !descs)) return TF_EINVAL;
     *out = nullptr;
-    tf_batch_config c = {2, 4, 8, 0};
+    tf_batch_config c = {2, 4, 16, 0};
     if (config) c = *config;
     if (!((c.ept64 == 2 && c.ept32 == 4) || (c.ept64 == 4 && c.ept32 == 4) ||
           (c.ept64 == 1 && c.ept32 == 2)) ||

@@ -1,9 +1,10 @@
 """Driver for rocprofv3 runs: a plain device copy of known size (the reference
 for scaling HBM byte counters), then each selected twofold kernel `reps` times
-on the benchmark's 2^26-element arrays.
+on 2^26-element arrays, binary64 then binary32.
 
-    rocprofv3 --pmc FETCH_SIZE --kernel-trace -f csv -d OUT -- \\
-        python3 -m paper_1502_05216_amd.profile_run --dtype f64 --reps 3
+    cd /tmp && export TMPDIR=/tmp
+    rocprofv3 --pmc FETCH_SIZE -f csv -d OUT -o run -- \\
+        python3 -m paper_1502_05216_amd.profile_run --dtype f64,f32 --reps 2
 
 Prints one line per step so a long run shows progress.
 """
@@ -15,7 +16,7 @@ import numpy as np
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--dtype", default="f64", choices=("f64", "f32"))
+    ap.add_argument("--dtype", default="f64", help="f64, f32 or f64,f32")
     ap.add_argument("--n", type=int, default=1 << 26)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--fn", default="all")
@@ -26,26 +27,26 @@ def main():
     from paper_1502_05216_amd import workloads
 
     dev = torch.device("cuda:0")
-    dt = np.float64 if args.dtype == "f64" else np.float32
-    tdt = torch.float64 if args.dtype == "f64" else torch.float32
-    src = torch.ones(args.n, dtype=tdt, device=dev)
+    src = torch.ones(args.n, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     print("copy of %d x %d bytes done" % (args.n, src.element_size()), flush=True)
     del src, dst
     funcs = tf.TWOFOLD if args.fn == "all" else tuple(args.fn.split(","))
-    for fn in funcs:
-        a, b = workloads.twofold_inputs(fn, args.n, dt)
-        x0 = torch.from_numpy(a).to(dev)
-        x1 = torch.from_numpy(b).to(dev)
-        z0 = torch.empty_like(x0)
-        z1 = torch.empty_like(x0)
-        for _ in range(args.reps):
-            getattr(tf, fn)(x0, x1, out=(z0, z1))
-        torch.cuda.synchronize()
-        print("%s %s x%d done" % (fn, args.dtype, args.reps), flush=True)
-        del x0, x1, z0, z1
+    for dname in args.dtype.split(","):
+        dt = {"f64": np.float64, "f32": np.float32}[dname]
+        for fn in funcs:
+            a, b = workloads.twofold_inputs(fn, args.n, dt)
+            x0 = torch.from_numpy(a).to(dev)
+            x1 = torch.from_numpy(b).to(dev)
+            z0 = torch.empty_like(x0)
+            z1 = torch.empty_like(x0)
+            for _ in range(args.reps):
+                getattr(tf, fn)(x0, x1, out=(z0, z1))
+            torch.cuda.synchronize()
+            print("%s %s x%d done" % (fn, dname, args.reps), flush=True)
+            del x0, x1, z0, z1
     return 0
 
 

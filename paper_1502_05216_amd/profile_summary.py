@@ -1,0 +1,193 @@
+"""Turns rocprofv3 CSV output into the short text summaries kept with the
+sources, and the per-launch HBM traffic table that bench.py reports.
+
+    # kernel durations per dispatch (rocprofv3 --kernel-trace -f csv); for the
+    # kernels matching --select, also the mean over dispatches skip..skip+take
+    # of each (the timed steps of bench.py after its warmup)
+    python -m paper_1502_05216_amd.profile_summary trace RUN_kernel_trace.csv \\
+        --title "..." --command "..." --select "k_twofold<double" --skip 3 --take 20 \\
+        --out profiles/NAME.md
+
+    # HBM bytes from two counter runs of profile_run (FETCH_SIZE, WRITE_SIZE)
+    python -m paper_1502_05216_amd.profile_summary traffic FETCH.csv WRITE.csv \\
+        --n 67108864 --command-fetch "..." --command-write "..." \\
+        --json profiles/traffic.json --out profiles/NAME.md
+
+Both counters are reported in KiB per dispatch.  They are scaled by what the
+same counter reads for a device-to-device copy of n binary64 values (n*8
+bytes read and n*8 bytes written), run first in the same process.
+"""
+import argparse
+import csv
+import json
+import re
+import sys
+from collections import defaultdict
+
+from ._build import source_hash
+
+FN_NAMES = {0: "texp", 1: "texpm1", 2: "tlog", 3: "tlog1p"}
+
+
+def short_name(kernel):
+    """Readable name of a kernel from its demangled signature."""
+    m = re.search(r"k_twofold<(double|float), (\d), (\d+), (\d+)>", kernel)
+    if m:
+        return "k_twofold<%s,%s> ept%s pd%s" % (m.group(1), FN_NAMES[int(m.group(2))],
+                                                m.group(3), m.group(4))
+    m = re.search(r"k_backward<(double|float), (\d), (\d+)>", kernel)
+    if m:
+        return "k_backward<%s,%s> ept%s" % (m.group(1), FN_NAMES[int(m.group(2))], m.group(3))
+    m = re.search(r"(k_batch\w*)<?([\d, ]*)>?", kernel)
+    if m:
+        return m.group(1) + ("<%s>" % m.group(2) if m.group(2) else "")
+    m = re.search(r"(k_onex)<(double|float), (\d)>", kernel)
+    if m:
+        return "k_onex<%s,%s>" % (m.group(2), m.group(3))
+    return kernel.split("(")[0][:60]
+
+
+def traffic_key(kernel):
+    m = re.search(r"k_twofold<(double|float), (\d),", kernel)
+    if not m:
+        return None
+    return ("f64_" if m.group(1) == "double" else "f32_") + FN_NAMES[int(m.group(2))]
+
+
+def stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    lines = ["# %s" % args.title, "", "Command (from the repository root):", "",
+             "    " + args.command.replace("\n", "\n    "), "",
+             "Source hash of paper_1502_05216_amd/csrc: %s" % source_hash(), "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r.get("Name") or r.get("KERNEL_NAME") or r.get("Kernel_Name")
+        avg = float(r.get("AverageNs") or r.get("Average_ns") or 0) / 1e3
+        mn = float(r.get("MinNs") or 0) / 1e3
+        mx = float(r.get("MaxNs") or 0) / 1e3
+        pct = float(r.get("Percentage") or 0)
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.1f%% |"
+                     % (short_name(name), r.get("Calls"), avg, mn, mx, pct))
+    if args.note:
+        lines += ["", args.note]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def trace(args):
+    groups = {}
+    for r in csv.DictReader(open(args.csv)):
+        key = (r["Kernel_Name"], int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        g = groups.setdefault(key, {"d": [], "first": int(r["Dispatch_Id"]), "r": r})
+        g["d"].append((int(r["Dispatch_Id"]),
+                       (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    lines = ["# %s" % args.title, "", "Command (from the repository root):", "",
+             "    " + args.command.replace("\n", "\n    "), "",
+             "Source hash of paper_1502_05216_amd/csrc: %s" % source_hash(), "",
+             "Durations in microseconds, from the kernel trace (end - start of each dispatch).",
+             "", "| kernel | grid x block | VGPR | LDS (B) | scratch (B) | dispatches | mean | "
+             "median | min | max | mean of selected |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (name, grid, block), g in sorted(groups.items(), key=lambda t: t[1]["first"]):
+        d = [t for _, t in sorted(g["d"])]
+        if len(d) < args.min_dispatches or sum(d) / len(d) < args.min_mean:
+            continue
+        ds = sorted(d)
+        sel = ""
+        if args.select and args.select in name:
+            part = d[args.skip:args.skip + args.take]
+            if part:
+                sel = "%.1f (%d..%d)" % (sum(part) / len(part), args.skip + 1,
+                                         args.skip + len(part))
+        r = g["r"]
+        lines.append("| %s | %d x %d | %s | %s | %s | %d | %.1f | %.1f | %.1f | %.1f | %s |"
+                     % (short_name(name), grid // block, block, r["VGPR_Count"],
+                        r["LDS_Block_Size"], r["Scratch_Size"], len(d), sum(d) / len(d),
+                        ds[len(ds) // 2], ds[0], ds[-1], sel))
+    if args.note:
+        lines += ["", args.note]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path, counter):
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic(args):
+    fetch = _per_kernel(args.fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(args.write_csv, "WRITE_SIZE")
+    copy_bytes = args.n * 8
+    cf = [v for k, vs in fetch.items() if "copyBuffer" in k for v in vs]
+    cw = [v for k, vs in write.items() if "copyBuffer" in k for v in vs]
+    if not cf or not cw:
+        sys.exit("no copy kernel in the counter runs")
+    f_scale = copy_bytes / (cf[0] * 1024)
+    w_scale = copy_bytes / (cw[0] * 1024)
+    h = source_hash()
+    out = {"src_hash": h, "n": args.n, "copy_bytes": copy_bytes,
+           "copy_fetch_kib": cf[0], "copy_write_kib": cw[0],
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    lines = ["# HBM traffic per launch of k_twofold, 2^26 elements (MI355X)", "",
+             "Counter runs (from the repository root; one counter per run):", "",
+             "    " + args.command_fetch, "    " + args.command_write, "",
+             "Source hash of paper_1502_05216_amd/csrc: %s" % h, "",
+             "Scale: a device-to-device copy of %d bytes reads FETCH_SIZE %.0f KiB and "
+             "WRITE_SIZE %.0f KiB, so FETCH_SIZE is multiplied by %.3f and WRITE_SIZE by %.3f."
+             % (copy_bytes, cf[0], cw[0], f_scale, w_scale), "",
+             "| kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | scaled bytes | "
+             "algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|"]
+    for k in sorted(fetch):
+        key = traffic_key(k)
+        if key is None or k not in write:
+            continue
+        fk = sum(fetch[k]) / len(fetch[k])
+        wk = sum(write[k]) / len(write[k])
+        b = fk * 1024 * f_scale + wk * 1024 * w_scale
+        alg = args.n * (32 if key.startswith("f64") else 16)
+        out["kernels"][key] = {"src_hash": h, "n": args.n, "bytes_per_launch": b,
+                               "algorithmic_bytes": alg, "fetch_kib": fk, "write_kib": wk,
+                               "dispatches": len(fetch[k])}
+        lines.append("| %s | %d | %.0f | %.0f | %.4g | %.4g | %.3f |"
+                     % (short_name(k), len(fetch[k]), fk, wk, b, alg, b / alg))
+    json.dump(out, open(args.json, "w"), indent=1)
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--note", default="")
+    s.add_argument("--out", required=True)
+    s = sub.add_parser("trace")
+    s.add_argument("csv")
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--select", default="")
+    s.add_argument("--skip", type=int, default=0)
+    s.add_argument("--take", type=int, default=1 << 30)
+    s.add_argument("--min-dispatches", type=int, default=2)
+    s.add_argument("--min-mean", type=float, default=0.0, help="drop groups with a smaller "
+                   "mean duration (us), e.g. the small per-array launches")
+    s.add_argument("--note", default="")
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--n", type=int, default=1 << 26)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    t.add_argument("--json", required=True)
+    t.add_argument("--out", required=True)
+    args = ap.parse_args()
+    {"stats": stats, "trace": trace, "traffic": traffic}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()
