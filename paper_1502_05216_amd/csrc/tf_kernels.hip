@@ -82,14 +82,19 @@ template <class T, bool EXP, bool PEXP0, bool PM1, bool LOG> struct Lds {
         }
     }
     __device__ ExpTab<T> et() const { return {S}; }
-    __device__ Pexp0Tab<T> pt() const { return {E, EK, C}; }
+    // Without the pexp0 tables in LDS (texpm1, which needs them only for its
+    // rare |x0| > ln 2 lanes) they are read from global memory (L1/L2 hits).
+    __device__ Pexp0Tab<T> pt() const {
+        if constexpr (PEXP0) return {E, EK, C};
+        else return {G<T>::E(), G<T>::EK(), G<T>::C()};
+    }
     __device__ Pm1Tab<T> mt() const { return {CM1}; }
     __device__ LogTab<T> lt() const { return {INVC, LG}; }
 };
 
 template <class T, int FN> struct LdsFor;
 template <class T> struct LdsFor<T, FN_TEXP> { using type = Lds<T, true, true, false, false>; };
-template <class T> struct LdsFor<T, FN_TEXPM1> { using type = Lds<T, true, true, true, false>; };
+template <class T> struct LdsFor<T, FN_TEXPM1> { using type = Lds<T, true, false, true, false>; };
 template <class T> struct LdsFor<T, FN_TLOG> { using type = Lds<T, false, false, true, true>; };
 template <class T> struct LdsFor<T, FN_TLOG1P> { using type = Lds<T, false, false, true, true>; };
 
@@ -404,10 +409,10 @@ struct BatchChunk {
 
 union BatchLds {
     Lds<double, true, true, false, false> d_exp;
-    Lds<double, true, true, true, false> d_expm1;
+    Lds<double, true, false, true, false> d_expm1;
     Lds<double, false, false, true, true> d_log;
     Lds<float, true, true, false, false> f_exp;
-    Lds<float, true, true, true, false> f_expm1;
+    Lds<float, true, false, true, false> f_expm1;
     Lds<float, false, false, true, true> f_log;
 };
 
@@ -569,11 +574,13 @@ struct LaunchCfg { int ept; int bpc; int pd; };
 // Defaults measured on MI355X (256 CUs) with paper_1502_05216_amd.tune on
 // 2^26-element arrays (beyond the last-level cache); the landscape is flat,
 // the best few configurations being within a few percent of each other.
+// More workgroups than fit at once (bpc 12-16) shorten the tail of the
+// grid-stride loop for the ALU-bound logarithms.
 LaunchCfg g_cfg[4][2] = {
-    {{4, 0, 1}, {4, 2, 1}},   // texp     {binary64, binary32}
-    {{1, 4, 1}, {2, 3, 1}},   // texpm1
-    {{2, 8, 1}, {4, 6, 2}},   // tlog
-    {{2, 8, 1}, {2, 0, 1}},   // tlog1p
+    {{4, 6, 2}, {4, 4, 1}},   // texp     {binary64, binary32}
+    {{1, 4, 1}, {1, 6, 2}},   // texpm1
+    {{2, 12, 2}, {4, 16, 2}}, // tlog
+    {{2, 12, 1}, {4, 16, 1}}, // tlog1p
 };
 LaunchCfg g_cfg1[4][2] = {
     {{2, 4, 1}, {4, 4, 1}},   // exp1x

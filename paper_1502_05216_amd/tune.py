@@ -7,9 +7,8 @@ For each function and format it times every candidate on seeded inputs of the
 benchmark distribution (at a size well beyond the last-level cache, so that
 HBM rather than cache bandwidth is measured), keeps the fastest, and writes a JSON cache keyed by
 the device (name, compute units) and the library version.  `apply()` loads the
-cache for the current device and sets the configuration in the library; the
-package calls it on first use of a kernel.  Without a cache the library's
-built-in defaults apply.
+cache for the current device and sets the configuration in the library.  The
+library's built-in defaults are the values this tuner found on MI355X.
 """
 import argparse
 import json
@@ -47,7 +46,8 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(n=1 << 26, reps=10, funcs=None, dtypes=("f64", "f32"), verbose=True):
+def tune(n=1 << 26, reps=10, funcs=None, dtypes=("f64", "f32"), verbose=True, epts=EPTS,
+         bpcs=BPCS):
     """Time all candidates; return {key: {"fn|dtype": [ept, bpc, pd, ms]}}."""
     import torch
     from . import workloads
@@ -69,8 +69,8 @@ def tune(n=1 << 26, reps=10, funcs=None, dtypes=("f64", "f32"), verbose=True):
                 call = lambda: _lib.onex_call(fn, x0, out=z0)
             old = _lib.get_launch_config(fn, dts)
             best = None
-            for ept in EPTS:
-                for bpc in BPCS:
+            for ept in epts:
+                for bpc in bpcs:
                     for pd in (PDS if fn in _lib.TWOFOLD else (1,)):
                         _lib.set_launch_config(fn, dts, ept, bpc, pd)
                         ms = _time(call, reps)
@@ -124,8 +124,14 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 26)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--funcs", default="", help="comma-separated subset, e.g. texpm1,tlog")
+    ap.add_argument("--dtypes", default="f64,f32")
+    ap.add_argument("--bpcs", default=",".join(map(str, BPCS)))
+    ap.add_argument("--epts", default=",".join(map(str, EPTS)))
     args = ap.parse_args()
-    r = tune(n=args.n, reps=args.reps)
+    r = tune(n=args.n, reps=args.reps, funcs=[f for f in args.funcs.split(",") if f] or None,
+             dtypes=tuple(args.dtypes.split(",")), bpcs=tuple(int(b) for b in args.bpcs.split(",")),
+             epts=tuple(int(e) for e in args.epts.split(",")))
     save(r, args.out)
     print(json.dumps(r, indent=1))
 
