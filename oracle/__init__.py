@@ -7,7 +7,10 @@ into oracle/libtfo.so) with numpy-array functions:
     z0, z1 = oracle.texp(x0, x1)        # and texpm1, tlog, tlog1p
     z0, z1 = oracle.texpf(x0, x1)       # binary32 variants
     z = oracle.exp1x(x)                 # the 1x main-part functions (+ f)
-    v0, v1 = oracle.pexp0(x)            # coupled p-functions (pins)
+    z0, z1 = oracle.pexp0(x)            # dotted argument: pexp0 texp0 pexpm10
+                                        # texpm10 plog0 tlog0 plog1p0 tlog1p0 (+ f)
+    z0, z1 = oracle.pexp(x0, x1)        # coupled argument: texpp pexp texpm1p
+                                        # pexpm1 tlogp plog tlog1pp plog1p (+ f)
     gx0, gx1 = oracle.texp_bwd(s0, s1, g0, g1)
     counts = oracle.op_count("texp", x0, x1)   # {add, mul, fma, other, n}
 
@@ -30,6 +33,9 @@ CXXFLAGS = ["-O2", "-mfma", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
 
 FUNCS_TW = ["texp", "texpm1", "tlog", "tlog1p"]
 FUNCS_1X = ["exp1x", "expm1_1x", "log1x", "log1p_1x"]
+# the other entry points of the paper's interface
+FUNCS_D = ["pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0"]
+FUNCS_C = ["texpp", "pexp", "texpm1p", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p"]
 
 
 def build(verbose=False):
@@ -73,9 +79,14 @@ def _load(path=None):
     for base in FUNCS_1X:
         for sfx in ("", "f"):
             getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, S, I]
-    for base in ("pexp0", "pexpm10"):
+    for base in FUNCS_C:
         for sfx in ("", "f"):
-            getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, P, S]
+            getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, P, P, S, I]
+            getattr(lib, "tfo_count_%s%s_n" % (base, sfx)).argtypes = [P, P, S, P]
+    for base in FUNCS_D:
+        for sfx in ("", "f"):
+            getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, P, S, I]
+            getattr(lib, "tfo_count_%s%s_n" % (base, sfx)).argtypes = [P, S, P]
     lib.tfo_eft_n.argtypes = [I, P, P, P, P, S]
     _libs[path] = lib
     return lib
@@ -120,15 +131,17 @@ def _mk_1x(name, dt, path=None):
     return f
 
 
-def _mk_p(name, dt, path=None):
-    def f(x):
+def _mk_d(name, dt, path=None):
+    def f(x, threads=1):
         lib = _load(path)
         x = _arr(x, dt)
         z0 = np.empty_like(x)
         z1 = np.empty_like(x)
-        getattr(lib, "tfo_%s_n" % name)(_ptr(x), _ptr(z0), _ptr(z1), x.size)
+        getattr(lib, "tfo_%s_n" % name)(_ptr(x), _ptr(z0), _ptr(z1), x.size, threads or 1)
         return z0, z1
     f.__name__ = name
+    f.__doc__ = "oracle %s over a %s array (dotted argument) -> (z0, z1)" % (name,
+                                                                          np.dtype(dt).name)
     return f
 
 
@@ -154,9 +167,12 @@ def _bind(ns, path=None):
     for b in FUNCS_1X:
         ns[b] = _mk_1x(b, np.float64, path)
         ns[b + "f"] = _mk_1x(b + "f", np.float32, path)
-    for b in ("pexp0", "pexpm10"):
-        ns[b] = _mk_p(b, np.float64, path)
-        ns[b + "f"] = _mk_p(b + "f", np.float32, path)
+    for b in FUNCS_C:
+        ns[b] = _mk_tw(b, np.float64, path)
+        ns[b + "f"] = _mk_tw(b + "f", np.float32, path)
+    for b in FUNCS_D:
+        ns[b] = _mk_d(b, np.float64, path)
+        ns[b + "f"] = _mk_d(b + "f", np.float32, path)
 
 
 _bind(globals())
@@ -184,8 +200,8 @@ def eft(which, a, b):
 def op_count(name, *arrays):
     """Floating-point operations the oracle performs for `name` over the given
     inputs: dict(add, mul, fma, other, n).  `name` is e.g. 'texp', 'tlogf',
-    'texp_bwd' (backward takes s0, s1, g0, g1).  add counts + and -, other
-    counts rint/ldexp/frexp and divisions."""
+    'texp_bwd' (backward takes s0, s1, g0, g1), 'plog0' (dotted argument: one
+    array).  add counts + and -, other counts rint/ldexp/frexp and divisions."""
     lib = _load()
     base = name[:-4] if name.endswith("_bwd") else name
     dt = np.float32 if base.endswith("f") else np.float64

@@ -484,18 +484,32 @@ template <class T> Tw<T> log_scale(Tw<T> w, int* n) {
     return w;
 }
 
-/* Newton step shared by plog and plog1p (section "Twofold logarithm: Newton
- * inversion"): with 1 + a the reduced argument,
- *   r0 = log1p(a0 + a1), s = pexpm10(-r0), u = (1+a)(1+s) - 1 = ((a s) + a) + s,
- *   r1 = u0 + u1, and, when add_n, (r0 + r1) + n ln2. */
-template <class T> Tw<T> plog_core(Tw<T> a, int n, bool add_n) {
-    using K = K_<T>;
-    T r0 = log1p_1x(a.x0 + a.x1);
+/* Newton correction (section "Twofold logarithm: Newton inversion"): for the
+ * reduced argument 1 + a and a seed r0 ~ log(1 + a),
+ *   s = pexpm10(-r0), u = (1+a)(1+s) - 1 = ((a s) + a) + s, r1 = u0 + u1.
+ * The reduction keeps |r0| <= ln 2; a seed beyond the small path of pexpm10
+ * (|r0| > 89/128, or not a number) arises only from an argument that is not
+ * coupled (or not finite) where the paper asks for a coupled one, and gives a
+ * NaN correction r1. */
+template <class T> Tw<T> newton_log(Tw<T> a, T r0) {
+    if (!(fabs(r0) <= T(0.6953125))) return {r0, qnan<T>()};
     Tw<T> s = pexpm10_small(-r0);
     Tw<T> u = add_tt(add_tt(mul_tt(a, s), a), s);
     T r1 = u.x0 + u.x1;
-    Tw<T> X = {r0, r1};
-    if (add_n) X = add_tt(X, mul_td(Tw<T>{T(K::LN2_HI()), T(K::LN2_LO())}, from_int<T>(n)));
+    return {r0, r1};
+}
+
+/* (r0 + r1) + n ln2, with n ln2 the twofold product of ln 2 and n. */
+template <class T> Tw<T> add_n_ln2(Tw<T> X, int n) {
+    using K = K_<T>;
+    return add_tt(X, mul_td(Tw<T>{T(K::LN2_HI()), T(K::LN2_LO())}, from_int<T>(n)));
+}
+
+/* Newton step shared by plog and plog1p: seed r0 = log1p(a0 + a1), the
+ * correction above, and, when add_n, (r0 + r1) + n ln2. */
+template <class T> Tw<T> plog_core(Tw<T> a, int n, bool add_n) {
+    Tw<T> X = newton_log(a, log1p_1x(a.x0 + a.x1));
+    if (add_n) X = add_n_ln2(X, n);
     return X;
 }
 
@@ -549,6 +563,210 @@ template <class T> T tlog1p(T y0, T y1, T* x1out) {
     return x0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The other entry points of the paper's interface (sections "Twofold         */
+/* exponent: Algorithm summary", "Twofold logarithm: Algorithm summary" and   */
+/* "C/C++ interface"): functions of a dotted argument x0 (x1 = 0), of a       */
+/* coupled argument, and p-functions whose result is coupled.  Every          */
+/* p-function ends with "renormalize fast"; inside a t-function that step is  */
+/* omitted, as the paper allows.                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Renormalize fast a result (|z0| >= |z1|), then the rule for a non-finite
+ * main part. */
+template <class T> T renorm_result(T z0, T z1, T* z1out) {
+    if (isnan(z0) || isinf(z0)) {
+        *z1out = special_rule(z0, z1);
+        return z0;
+    }
+    Tw<T> r = fast_two_sum(z0, z1);
+    *z1out = special_rule(r.x0, r.x1);
+    return r.x0;
+}
+
+/* pexp0 and pexpm10 in the scalar form of the interface. */
+template <class T> T pexp0_s(T x0, T* z1) { Tw<T> r = pexp0(x0); *z1 = r.x1; return r.x0; }
+template <class T> T pexpm10_s(T x0, T* z1) { Tw<T> r = pexpm10(x0); *z1 = r.x1; return r.x0; }
+
+/* texp0 (dotted argument): v = pexp0(x0) not renormalised, z0 = exp(x0),
+ * z1 = (v0 - z0) + v1, in pexp0's 2^-k domain as texp. */
+template <class T> T texp0(T x0, T* z1out) {
+    using K = K_<T>;
+    T z0 = exp1x(x0);
+    T z1;
+    if (isnan(z0) || isinf(z0)) {
+        z1 = T(0);                                     /* replaced by the rule */
+    } else if (x0 < T(K::EXP_XLO())) {
+        Tw<T> v = {T(0), T(0)};                        /* pexp0 gives 0 below range */
+        z1 = (v.x0 - z0) + v.x1;
+    } else {
+        Scaled<T> s = pexp0_core(x0);
+        T z0s = ldexp(z0, -s.k);                       /* exact */
+        z1 = ldexp((s.v.x0 - z0s) + s.v.x1, s.k);
+    }
+    *z1out = special_rule(z0, z1);
+    return z0;
+}
+
+/* texpm10 (dotted argument): w = pexpm10(x0) not renormalised,
+ * z0 = expm1(x0), z1 = (w0 - z0) + w1. */
+template <class T> T texpm10(T x0, T* z1out) {
+    T z0 = expm1_1x(x0);
+    T z1 = T(0);
+    if (!(isnan(z0) || isinf(z0))) {
+        Tw<T> w = pexpm10_body(x0);
+        z1 = (w.x0 - z0) + w.x1;
+    }
+    *z1out = special_rule(z0, z1);
+    return z0;
+}
+
+/* texpp and texpm1p (coupled argument): the paper gives no special algorithm
+ * for a coupled argument; they are texp and texpm1. */
+template <class T> T texpp(T x0, T x1, T* z1) { return texp(x0, x1, z1); }
+template <class T> T texpm1p(T x0, T x1, T* z1) { return texpm1(x0, x1, z1); }
+
+/* pexp and pexpm1 (coupled argument, coupled result): texpp and texpm1p,
+ * then renormalize fast. */
+template <class T> T pexp(T x0, T x1, T* z1out) {
+    T z1;
+    T z0 = texpp(x0, x1, &z1);
+    return renorm_result(z0, z1, z1out);
+}
+template <class T> T pexpm1(T x0, T x1, T* z1out) {
+    T z1;
+    T z0 = texpm1p(x0, x1, &z1);
+    return renorm_result(z0, z1, z1out);
+}
+
+/* plog0 steps (1)-(3), dotted y0 in (0, inf), not renormalised:
+ * y0 = 2^n z0, r0 = log(z0) (the 1x log), the Newton correction with
+ * 1 + a = z0, then + n ln2. */
+template <class T> Tw<T> plog0_core(T y0) {
+    int n;
+    Tw<T> z = log_scale(Tw<T>{y0, T(0)}, &n);
+    Tw<T> a = {z.x0 - T(1), z.x1};                     /* exact (Sterbenz) */
+    return add_n_ln2(newton_log(a, log1x(z.x0)), n);
+}
+
+/* plog (coupled argument) steps (1)-(3), y0 in (0, inf), not renormalised:
+ * y = 2^n (z0 + z1) scaled by the exponent of y0, a = (z0 - 1) + z1, the
+ * Newton step seeded with log1p(a0 + a1), then + n ln2. */
+template <class T> Tw<T> plog_coupled_core(Tw<T> y) {
+    int n;
+    Tw<T> z = log_scale(y, &n);
+    Tw<T> a = {z.x0 - T(1), z.x1};
+    return plog_core(a, n, true);
+}
+
+/* plog1p0 steps (1)-(2), dotted y0 in (-1, inf), not renormalised: outside
+ * [-1/2, 1] the plog of the renormalised 1 + y0; inside, x0 = log1p(y0) and
+ * the Newton correction with a = y0 (the text's "pexpm10(-r0)" is read as
+ * pexpm10(-x0), the seed just computed). */
+template <class T> Tw<T> plog1p0_core(T y0) {
+    if (y0 < T(-0.5) || y0 > T(1)) return plog_coupled_core(two_sum(T(1), y0));
+    return newton_log(Tw<T>{y0, T(0)}, log1p_1x(y0));
+}
+
+/* plog1p (coupled argument) steps (1)-(2), y0 in (-1, inf), not
+ * renormalised: outside [-1/2, 1] the plog of the renormalised 1 + y (the
+ * text's tlogp(1 + y) differs from plog only in an x0 correction that the
+ * p-function does not want); inside, the Newton step on a = y, seeded with
+ * log1p(y0 + y1), which is log1p(y0) for a coupled y. */
+template <class T> Tw<T> plog1p_core(Tw<T> y) {
+    if (y.x0 < T(-0.5) || y.x0 > T(1)) {
+        Tw<T> w = add_td(y, T(1));
+        return plog_coupled_core(two_sum(w.x0, w.x1));
+    }
+    return plog_core(y, 0, false);
+}
+
+/* The p-functions of the logarithm: main part outside the domain of the 1x
+ * function -> that function's value (-inf, +inf or NaN) and the rule;
+ * otherwise the core, renormalised fast. */
+template <class T> T plog0(T y0, T* x1out) {
+    if (!(y0 > T(0) && y0 < pinf<T>())) {
+        T x0 = log1x(y0);
+        *x1out = special_rule(x0, T(0));
+        return x0;
+    }
+    Tw<T> X = plog0_core(y0);
+    return renorm_result(X.x0, X.x1, x1out);
+}
+template <class T> T plog(T y0, T y1, T* x1out) {
+    if (!(y0 > T(0) && y0 < pinf<T>())) {
+        T x0 = log1x(y0);
+        *x1out = special_rule(x0, T(0));
+        return x0;
+    }
+    Tw<T> X = plog_coupled_core(Tw<T>{y0, y1});
+    return renorm_result(X.x0, X.x1, x1out);
+}
+template <class T> T plog1p0(T y0, T* x1out) {
+    if (!(y0 > T(-1) && y0 < pinf<T>())) {
+        T x0 = log1p_1x(y0);
+        *x1out = special_rule(x0, T(0));
+        return x0;
+    }
+    Tw<T> X = plog1p0_core(y0);
+    return renorm_result(X.x0, X.x1, x1out);
+}
+template <class T> T plog1p(T y0, T y1, T* x1out) {
+    if (!(y0 > T(-1) && y0 < pinf<T>())) {
+        T x0 = log1p_1x(y0);
+        *x1out = special_rule(x0, T(0));
+        return x0;
+    }
+    Tw<T> X = plog1p_core(Tw<T>{y0, y1});
+    return renorm_result(X.x0, X.x1, x1out);
+}
+
+/* The t-functions: the core not renormalised, then the correction that makes
+ * the main part the 1x function bitwise: u0 = log(y0) (or log1p(y0)),
+ * x1 = X1 + (X0 - u0), x0 = u0.  (The text writes the correction of tlog0 and
+ * tlog1p0 as x1 + (u0 - x0); the sign that keeps x0 + x1 is X0 - u0, as in
+ * tlog's own last step.) */
+template <class T> T tlog0(T y0, T* x1out) {
+    T u0 = log1x(y0);
+    T x1 = T(0);
+    if (!(isnan(u0) || isinf(u0))) {
+        Tw<T> X = plog0_core(y0);
+        x1 = X.x1 + (X.x0 - u0);
+    }
+    *x1out = special_rule(u0, x1);
+    return u0;
+}
+template <class T> T tlogp(T y0, T y1, T* x1out) {
+    T u0 = log1x(y0);
+    T x1 = T(0);
+    if (!(isnan(u0) || isinf(u0))) {
+        Tw<T> X = plog_coupled_core(Tw<T>{y0, y1});
+        x1 = X.x1 + (X.x0 - u0);
+    }
+    *x1out = special_rule(u0, x1);
+    return u0;
+}
+template <class T> T tlog1p0(T y0, T* x1out) {
+    T u0 = log1p_1x(y0);
+    T x1 = T(0);
+    if (!(isnan(u0) || isinf(u0))) {
+        Tw<T> X = plog1p0_core(y0);
+        x1 = X.x1 + (X.x0 - u0);
+    }
+    *x1out = special_rule(u0, x1);
+    return u0;
+}
+template <class T> T tlog1pp(T y0, T y1, T* x1out) {
+    T u0 = log1p_1x(y0);
+    T x1 = T(0);
+    if (!(isnan(u0) || isinf(u0))) {
+        Tw<T> X = plog1p_core(Tw<T>{y0, y1});
+        x1 = X.x1 + (X.x0 - u0);
+    }
+    *x1out = special_rule(u0, x1);
+    return u0;
+}
+
 /* Backward (twofold adjoints, not in the paper): for x = x0 + x1 and the saved
  * forward value s (z for texp/texpm1, y for tlog/tlog1p), given the twofold
  * upstream gradient g:  texp g*z, texpm1 g*(z + 1), tlog g/y, tlog1p g/(1 + y). */
@@ -574,12 +792,11 @@ void run_1x(const T* x, T* z, size_t n, int threads) {
     for (long long i = 0; i < (long long)n; ++i) z[i] = F(x[i]);
 }
 
-template <class T, Tw<T> (*F)(T)>
-void run_p(const T* x, T* z0, T* z1, size_t n) {
-    for (size_t i = 0; i < n; ++i) {
-        Tw<T> r = F(x[i]);
-        z0[i] = r.x0; z1[i] = r.x1;
-    }
+template <class T, T (*F)(T, T*)>
+void run_d(const T* x, T* z0, T* z1, size_t n, int threads) {
+    if (threads < 1) threads = 1;
+#pragma omp parallel for schedule(static) num_threads(threads)
+    for (long long i = 0; i < (long long)n; ++i) z0[i] = F(x[i], &z1[i]);
 }
 
 template <class T, Tw<T> (*F)(Tw<T>, Tw<T>)>
@@ -600,6 +817,16 @@ void count_tw(const U* x0, const U* x1, size_t n, unsigned long long* out) {
     for (size_t i = 0; i < n; ++i) {
         Cnt<U> z1;
         (void)F(Cnt<U>(x0[i]), Cnt<U>(x1[i]), &z1);
+    }
+    out[0] = g_cnt.add; out[1] = g_cnt.mul; out[2] = g_cnt.fma; out[3] = g_cnt.other;
+}
+
+template <class U, Cnt<U> (*F)(Cnt<U>, Cnt<U>*)>
+void count_d(const U* x, size_t n, unsigned long long* out) {
+    g_cnt = OpCount{0, 0, 0, 0};
+    for (size_t i = 0; i < n; ++i) {
+        Cnt<U> z1;
+        (void)F(Cnt<U>(x[i]), &z1);
     }
     out[0] = g_cnt.add; out[1] = g_cnt.mul; out[2] = g_cnt.fma; out[3] = g_cnt.other;
 }
@@ -638,6 +865,23 @@ TFO_TW(texpm1f, float, texpm1)
 TFO_TW(tlogf, float, tlog)
 TFO_TW(tlog1pf, float, tlog1p)
 
+TFO_TW(texpp, double, texpp)
+TFO_TW(pexp, double, pexp)
+TFO_TW(texpm1p, double, texpm1p)
+TFO_TW(pexpm1, double, pexpm1)
+TFO_TW(tlogp, double, tlogp)
+TFO_TW(plog, double, plog)
+TFO_TW(tlog1pp, double, tlog1pp)
+TFO_TW(plog1p, double, plog1p)
+TFO_TW(texppf, float, texpp)
+TFO_TW(pexpf, float, pexp)
+TFO_TW(texpm1pf, float, texpm1p)
+TFO_TW(pexpm1f, float, pexpm1)
+TFO_TW(tlogpf, float, tlogp)
+TFO_TW(plogf, float, plog)
+TFO_TW(tlog1ppf, float, tlog1pp)
+TFO_TW(plog1pf, float, plog1p)
+
 #define TFO_1X(NAME, T, FN)                                                                  \
     T tfo_##NAME(T x) { return FN<T>(x); }                                                  \
     void tfo_##NAME##_n(const T* x, T* z, size_t n, int threads) { run_1x<T, FN<T>>(x, z, n, threads); }
@@ -651,13 +895,31 @@ TFO_1X(expm1_1xf, float, expm1_1x)
 TFO_1X(log1xf, float, log1x)
 TFO_1X(log1p_1xf, float, log1p_1x)
 
-#define TFO_P(NAME, T, FN)                                                       \
-    void tfo_##NAME##_n(const T* x, T* z0, T* z1, size_t n) { run_p<T, FN<T>>(x, z0, z1, n); }
+#define TFO_D(NAME, T, FN)                                                                \
+    T tfo_##NAME(T x, T* z1) { return FN<T>(x, z1); }                                        \
+    void tfo_##NAME##_n(const T* x, T* z0, T* z1, size_t n, int threads) {                  \
+        run_d<T, FN<T>>(x, z0, z1, n, threads);                                               \
+    }                                                                                         \
+    void tfo_count_##NAME##_n(const T* x, size_t n, unsigned long long* out) {              \
+        count_d<T, FN<Cnt<T>>>(x, n, out);                                                    \
+    }
 
-TFO_P(pexp0, double, pexp0)
-TFO_P(pexpm10, double, pexpm10)
-TFO_P(pexp0f, float, pexp0)
-TFO_P(pexpm10f, float, pexpm10)
+TFO_D(pexp0, double, pexp0_s)
+TFO_D(texp0, double, texp0)
+TFO_D(pexpm10, double, pexpm10_s)
+TFO_D(texpm10, double, texpm10)
+TFO_D(plog0, double, plog0)
+TFO_D(tlog0, double, tlog0)
+TFO_D(plog1p0, double, plog1p0)
+TFO_D(tlog1p0, double, tlog1p0)
+TFO_D(pexp0f, float, pexp0_s)
+TFO_D(texp0f, float, texp0)
+TFO_D(pexpm10f, float, pexpm10_s)
+TFO_D(texpm10f, float, texpm10)
+TFO_D(plog0f, float, plog0)
+TFO_D(tlog0f, float, tlog0)
+TFO_D(plog1p0f, float, plog1p0)
+TFO_D(tlog1p0f, float, tlog1p0)
 
 #define TFO_BWD(NAME, T, FN)                                                                   \
     void tfo_##NAME##_n(const T* s0, const T* s1, const T* g0, const T* g1, T* gx0, T* gx1,   \

@@ -89,7 +89,20 @@ def _x0(fn, n, dt, rng):
     return x.astype(dt)
 
 
-def twofold_inputs(fn, n, dtype=np.float64, seed=SEED, edges=0.001, x0_range=None):
+# The other entry points of the paper's interface, by the argument recipe
+# they share with one of the four twofold functions.
+INTERFACE_BASE = {
+    "pexp0": "texp", "texp0": "texp", "texpp": "texp", "pexp": "texp",
+    "pexpm10": "texpm1", "texpm10": "texpm1", "texpm1p": "texpm1", "pexpm1": "texpm1",
+    "plog0": "tlog", "tlog0": "tlog", "tlogp": "tlog", "plog": "tlog",
+    "plog1p0": "tlog1p", "tlog1p0": "tlog1p", "tlog1pp": "tlog1p", "plog1p": "tlog1p",
+}
+DOTTED = ("pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0")
+COUPLED = ("texpp", "pexp", "texpm1p", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p")
+
+
+def twofold_inputs(fn, n, dtype=np.float64, seed=SEED, edges=0.001, x0_range=None,
+                   coupled=False):
     """Twofold arguments (x0, x1) for fn: n elements of dtype, seeded.
 
     texp: x0 ~ U[-745, 709.7] (float U[-103.9, 88.7]); tlog: x0 = 2^U[-1074, 1023]
@@ -98,7 +111,10 @@ def twofold_inputs(fn, n, dtype=np.float64, seed=SEED, edges=0.001, x0_range=Non
     indices (chosen by the same generator) takes values from edge_values(fn)
     with x1 = 0, except every 8th of them, whose x1 cycles through
     +inf, -inf, NaN and the least subnormal.  x0_range=(lo, hi) replaces the
-    x0 law by U[lo, hi]."""
+    x0 law by U[lo, hi].  coupled=True halves eps, so that x0 + x1 rounds to x0
+    (the arguments of the paper's coupled-argument functions).  fn may also
+    name one of the other interface functions (INTERFACE_BASE)."""
+    fn = INTERFACE_BASE.get(fn, fn)
     dt = np.dtype(dtype).type
     rng = _rng(seed)
     if x0_range is None:
@@ -107,8 +123,12 @@ def twofold_inputs(fn, n, dtype=np.float64, seed=SEED, edges=0.001, x0_range=Non
         x0 = rng.uniform(x0_range[0], x0_range[1], n).astype(dt)
     u = rng.uniform(-1.0, 1.0, n).astype(dt)
     with np.errstate(over="ignore", invalid="ignore", under="ignore"):
-        x1 = (x0 * u) * _eps(dt)
-    x1 = x1.astype(dt)
+        x1 = (x0 * u) * (_eps(dt) / dt(2) if coupled else _eps(dt))
+        x1 = x1.astype(dt)
+        if coupled:
+            # near the subnormal range x1 rounds onto a coarse grid and can
+            # reach half an ulp of x0: drop it there
+            x1[(x0 + x1) != x0] = dt(0.0)
     ne = int(round(n * edges))
     if ne > 0:
         ev = edge_values(fn, dt)

@@ -36,7 +36,48 @@ MUTANTS = {
     "log table index": ("T r = fma(z, T(K::LOG_INVC()[i]), T(-1)); /* exact */",
                         "T r = fma(z, T(K::LOG_INVC()[i ^ 1]), T(-1));"),
     "exp table low part": ("T y = s + fma(s, p, T(K::S_LO()[j]));", "T y = s + fma(s, p, T(0));"),
+    # the other entry points of the interface
+    "tlog0 correction sign": ("x1 = X.x1 + (X.x0 - u0);", "x1 = X.x1 + (u0 - X.x0);"),
+    "plog0 dropped n ln2": ("return add_n_ln2(newton_log(a, log1x(z.x0)), n);",
+                            "return newton_log(a, log1x(z.x0));"),
+    "plog1p0 outer sign": ("return plog_coupled_core(two_sum(T(1), y0));",
+                           "return plog_coupled_core(two_sum(T(1), -y0));"),
+    "texp0 dropped v1": ("z1 = ldexp((s.v.x0 - z0s) + s.v.x1, s.k);",
+                         "z1 = ldexp((s.v.x0 - z0s), s.k);"),
+    "p-function not renormalised": ("Tw<T> r = fast_two_sum(z0, z1);", "Tw<T> r = {z0, z1};"),
+    "plog1p outer 1 + y": ("Tw<T> w = add_td(y, T(1));\n        return plog_coupled_core",
+                           "Tw<T> w = add_td(y, T(-1));\n        return plog_coupled_core"),
 }
+
+
+def battery_interface(o):
+    """Accuracy of the other interface functions (and coupling of the
+    p-functions' results) on a few hundred arguments each."""
+    math_of = {"texp": "exp", "texpm1": "expm1", "tlog": "log", "tlog1p": "log1p"}
+    for name in ("texp0", "pexp", "plog0", "tlog0", "plog1p0", "tlog1pp", "plog1p"):
+        base = workloads.INTERFACE_BASE[name]
+        x0, x1 = workloads.twofold_inputs(name, 300, np.float64, seed=8, edges=0.0,
+                                          coupled=name in workloads.COUPLED)
+        if name in workloads.DOTTED:
+            x1 = np.zeros_like(x0)
+            z0, z1 = getattr(o, name)(x0)
+        else:
+            z0, z1 = getattr(o, name)(x0, x1)
+        if name.startswith("p"):
+            fin = np.isfinite(z0)
+            if not ((z0[fin] + z1[fin]) == z0[fin]).all():
+                return False
+        rel = []
+        for a, b, c, d in zip(x0, x1, z0, z1):
+            v = mpref.exact(math_of[base], a, b)
+            if v is None or abs(v) < 2.0 ** -969:
+                continue
+            if not np.isfinite(c) or not np.isfinite(d):
+                return False
+            rel.append(mpref.rel_error(c, d, v))
+        if max(rel) > 2.0 ** -93:
+            return False
+    return True
 
 
 def battery(o):
@@ -64,7 +105,7 @@ def battery(o):
                 if mpref.exact(fn, xi) is not None and abs(float(mpref.exact(fn, xi))) > 2.0 ** -1022]
         if max(errs) > 0.52 or np.mean(errs) > 0.3:
             return False
-    return True
+    return battery_interface(o)
 
 
 def test_unmodified_source_passes(tmp_path):
