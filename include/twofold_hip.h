@@ -91,6 +91,94 @@ tf_status tf_expm1_1xf(const float* x, float* z, size_t n, void* stream);
 tf_status tf_log1xf(const float* x, float* z, size_t n, void* stream);
 tf_status tf_log1p_1xf(const float* x, float* z, size_t n, void* stream);
 
+/* --- the other entry points of the paper's interface --------------------
+ * Section "C/C++ interface" lists, besides texp/texpm1/tlog/tlog1p, the
+ * functions below (algorithms: sections "Twofold exponent: Algorithm
+ * summary" and "Twofold logarithm: Algorithm summary").  Conventions as
+ * above; add "f" for binary32 (same signature with float).
+ *
+ * Dotted argument (an ordinary number x0; x1 = 0), one input array:
+ *   pexp0    coupled e^x0: 0 below ln 2^min, z0 = z1 = +inf above ln 2^max,
+ *            else E (C T) renormalised fast (z0 + z1 rounds to z0)
+ *   texp0    z0 = exp(x0) bitwise, z1 = (v0 - z0) + v1 with v = pexp0(x0)
+ *   pexpm10  coupled e^x0 - 1 (small-path table for |x0| <= ln 2, else
+ *            pexp0(x0) - 1); +inf above ln 2^max
+ *   texpm10  z0 = expm1(x0) bitwise, z1 = (w0 - z0) + w1, w = pexpm10(x0)
+ *   plog0    coupled log y0: y0 = 2^n z0, seed log(z0), one Newton step on
+ *            pexpm10, + n ln2, renormalised fast
+ *   tlog0    z0 = log(y0) bitwise, z1 = X1 + (X0 - z0) with X = plog0(y0)
+ *            (not renormalised)
+ *   plog1p0  coupled log(1 + y0): for y0 outside [-1/2, 1] plog of the
+ *            renormalised 1 + y0, else the Newton step seeded with log1p(y0)
+ *   tlog1p0  z0 = log1p(y0) bitwise, z1 = X1 + (X0 - z0), X = plog1p0(y0)
+ * The p-functions of the logarithm return, for y0 outside the domain of the
+ * 1x function (y0 <= 0, resp. y0 <= -1, +inf, NaN), that function's value
+ * and the rule for z1.
+ *
+ * Coupled argument (x0 + x1 rounds to x0), two input arrays:
+ *   texpp, texpm1p   texp and texpm1 (no special algorithm for a coupled
+ *                    argument; they run the same kernels)
+ *   pexp, pexpm1     texpp, texpm1p renormalised fast (coupled result)
+ *   plog             coupled log: scaled by the exponent of y0 (no
+ *                    renormalisation of y first), Newton step, + n ln2,
+ *                    renormalised fast
+ *   tlogp            z0 = log(y0) bitwise, z1 = X1 + (X0 - z0), X = plog(y)
+ *   plog1p           coupled log(1 + y): plog of the renormalised 1 + y
+ *                    outside [-1/2, 1], else the Newton step on a = y
+ *   tlog1pp          z0 = log1p(y0) bitwise, z1 = X1 + (X0 - z0)
+ * An argument that is not coupled where a coupled one is due (or a non-finite
+ * y1) gives z1 = NaN when the Newton step's seed leaves its range.
+ */
+tf_status tf_pexp0(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_texp0(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_pexpm10(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_texpm10(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_plog0(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_tlog0(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_plog1p0(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_tlog1p0(const double* x0, double* z0, double* z1, size_t n, void* stream);
+tf_status tf_pexp0f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_texp0f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_pexpm10f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_texpm10f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_plog0f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_tlog0f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_plog1p0f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+tf_status tf_tlog1p0f(const float* x0, float* z0, float* z1, size_t n, void* stream);
+
+tf_status tf_texpp(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                   void* stream);
+tf_status tf_pexp(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                  void* stream);
+tf_status tf_texpm1p(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                     void* stream);
+tf_status tf_pexpm1(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                    void* stream);
+tf_status tf_tlogp(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                   void* stream);
+tf_status tf_plog(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                  void* stream);
+tf_status tf_tlog1pp(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                     void* stream);
+tf_status tf_plog1p(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                    void* stream);
+tf_status tf_texppf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                    void* stream);
+tf_status tf_pexpf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                   void* stream);
+tf_status tf_texpm1pf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                      void* stream);
+tf_status tf_pexpm1f(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                     void* stream);
+tf_status tf_tlogpf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                    void* stream);
+tf_status tf_plogf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                   void* stream);
+tf_status tf_tlog1ppf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                      void* stream);
+tf_status tf_plog1pf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                     void* stream);
+
 /* --- backward (twofold adjoints; not part of the paper) ----------------
  * Gradient of a twofold function with respect to its twofold argument
  * x = x0 + x1, given the twofold upstream gradient g = g0 + g1 and the saved

@@ -8,6 +8,11 @@ GPU, in binary64 and binary32:
     z0, z1 = tlog(x0, x1)      # log
     z0, z1 = tlog1p(x0, x1)    # log1p
     z = exp1x(x), expm1_1x(x), log1x(x), log1p_1x(x)   # the 1x main parts
+    z0, z1 = pexp0(x0), texp0(x0), pexpm10(x0), texpm10(x0),
+             plog0(y0), tlog0(y0), plog1p0(y0), tlog1p0(y0)  # dotted argument
+    z0, z1 = texpp(x0, x1), pexp(x0, x1), texpm1p(x0, x1), pexpm1(x0, x1),
+             tlogp(y0, y1), plog(y0, y1), tlog1pp(y0, y1), plog1p(y0, y1)
+                                                        # coupled argument
     gx0, gx1 = texp_bwd(z0, z1, g0, g1)                 # twofold adjoints
     autograd.TExp / TExpm1 / TLog / TLog1p              # torch.autograd.Function
 
@@ -15,8 +20,8 @@ Arguments are contiguous torch tensors on the GPU; work is enqueued on the
 current stream.  The kernels live in libtwofold_hip.so (csrc/, C ABI in
 include/twofold_hip.h); this package only marshals arguments.
 """
-from ._lib import (ONEX, TWOFOLD, TwofoldError, backward_call, declared_functions, lib,
-                   onex_call, twofold_call)
+from ._lib import (COUPLED, DOTTED, ONEX, TWOFOLD, TwofoldError, backward_call,
+                   declared_functions, dotted_call, lib, onex_call, twofold_call)
 
 
 def texp(x0, x1, out=None):
@@ -67,6 +72,28 @@ def tlog1p_bwd(s0, s1, g0, g1, out=None):
     return backward_call("tlog1p", s0, s1, g0, g1, out)
 
 
+def _dotted(name):
+    def f(x0, out=None):
+        return dotted_call(name, x0, out)
+    f.__name__ = name
+    f.__doc__ = "z0, z1 = %s(x0) elementwise (dotted argument)" % name
+    return f
+
+
+def _coupled(name):
+    def f(x0, x1, out=None):
+        return twofold_call(name, x0, x1, out)
+    f.__name__ = name
+    f.__doc__ = "z0, z1 = %s(x0 + x1) elementwise (coupled argument)" % name
+    return f
+
+
+for _n in DOTTED:
+    globals()[_n] = _dotted(_n)
+for _n in COUPLED:
+    globals()[_n] = _coupled(_n)
+
+
 def build(verbose=False):
     from . import _build
     return _build.build(verbose=verbose)
@@ -74,4 +101,5 @@ def build(verbose=False):
 
 __all__ = ["texp", "texpm1", "tlog", "tlog1p", "exp1x", "expm1_1x", "log1x", "log1p_1x",
            "texp_bwd", "texpm1_bwd", "tlog_bwd", "tlog1p_bwd",
-           "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX"]
+           "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX",
+           "DOTTED", "COUPLED"] + list(DOTTED) + list(COUPLED)

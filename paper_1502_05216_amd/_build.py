@@ -1,12 +1,15 @@
 """Builds libtwofold_hip.so (HIP, gfx950) in-tree with hipcc."""
 import hashlib
 import os
+import shutil
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtwofold_hip.so")
-SOURCES = [os.path.join(PKG, "csrc", "tf_kernels.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "tf_kernels.hip"), os.path.join(PKG, "csrc", "tf_iface.hip")]
 ARCH = os.environ.get("TF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -14,7 +17,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # every fused multiply-add is explicit: no contraction of a*b+c
     "-ffp-contract=off",
     # keep binary32 subnormals (the float twofolds reach them)
@@ -32,10 +34,7 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False, extra=()):
-    """Compile the library (always recompiles) and return its path."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + list(extra) + SOURCES + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd))
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -46,7 +45,25 @@ def build(verbose=False, extra=()):
         raise RuntimeError("hipcc failed:\n" + out)
     if verbose and out.strip():
         print(out)
-    os.replace(tmp, LIB)
+
+
+def build(verbose=False, extra=()):
+    """Compile the library (always recompiles: one object per source, in
+    parallel, then the shared-library link) and return its path."""
+    tmpdir = tempfile.mkdtemp(prefix="tf_build_")
+    try:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[hipcc()] + HIPCC_FLAGS + list(extra) + ["-c", src, "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp],
+             verbose)
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

@@ -19,6 +19,9 @@ TF_OK, TF_EINVAL, TF_ELAUNCH, TF_ENOMEM, TF_EUNSUPPORTED, TF_ENODEV = range(6)
 
 TWOFOLD = ("texp", "texpm1", "tlog", "tlog1p")
 ONEX = ("exp1x", "expm1_1x", "log1x", "log1p_1x")
+# the other entry points of the paper's interface
+DOTTED = ("pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0")
+COUPLED = ("texpp", "pexp", "texpm1p", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p")
 
 _lib = None
 
@@ -38,10 +41,15 @@ def _load():
         raise RuntimeError("libtwofold_hip.so is not built (run __graft_entry__.build())")
     lib = ctypes.CDLL(LIB_PATH)
     P, S = ctypes.c_void_p, ctypes.c_size_t
-    for f in TWOFOLD:
+    for f in TWOFOLD + COUPLED:
         for sfx in ("", "f"):
             fn = getattr(lib, "tf_" + f + sfx)
             fn.argtypes = [P, P, P, P, S, P]
+            fn.restype = ctypes.c_int
+    for f in DOTTED:
+        for sfx in ("", "f"):
+            fn = getattr(lib, "tf_" + f + sfx)
+            fn.argtypes = [P, P, P, S, P]
             fn.restype = ctypes.c_int
     for f in ONEX:
         for sfx in ("", "f"):
@@ -108,9 +116,9 @@ def _validate(*ts):
 
 
 def twofold_call(name, x0, x1, out=None):
-    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD."""
+    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD or COUPLED."""
     import torch
-    if name not in TWOFOLD:
+    if name not in TWOFOLD + COUPLED:
         raise ValueError(name)
     _validate(x0, x1)
     if out is None:
@@ -123,6 +131,25 @@ def twofold_call(name, x0, x1, out=None):
     with torch.cuda.device(x0.device):
         _check(fn(x0.data_ptr(), x1.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(),
                   _stream()), "tf_" + name)
+    return z0, z1
+
+
+def dotted_call(name, x0, out=None):
+    """z0, z1 = name(x0) elementwise for a dotted argument; name in DOTTED."""
+    import torch
+    if name not in DOTTED:
+        raise ValueError(name)
+    _validate(x0)
+    if out is None:
+        z0 = torch.empty_like(x0)
+        z1 = torch.empty_like(x0)
+    else:
+        z0, z1 = out
+        _validate(x0, z0, z1)
+    fn = getattr(_load(), "tf_" + name + _suffix(x0))
+    with torch.cuda.device(x0.device):
+        _check(fn(x0.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(), _stream()),
+               "tf_" + name)
     return z0, z1
 
 

@@ -1,0 +1,162 @@
+// Shared pieces of the library's translation units: the LDS images of the
+// tables, vector loads/stores of a thread's elements, and host-side launch
+// helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+
+#include "../../include/twofold_hip.h"
+#include "tf_device.hpp"
+
+namespace tfk {
+
+using namespace tfh;
+
+constexpr int kBlock = 256;
+
+enum Fn : int { FN_TEXP = 0, FN_TEXPM1 = 1, FN_TLOG = 2, FN_TLOG1P = 3 };
+enum Fn1 : int { F1_EXP = 0, F1_EXPM1 = 1, F1_LOG = 2, F1_LOG1P = 3 };
+
+// Global copies of the tables (tf_tables.inc), per format.
+template <class T> struct G;
+template <> struct G<double> {
+    __device__ static const double2* E() { return TFH_D_E; }
+    __device__ static const int* EK() { return TFH_D_EK; }
+    __device__ static const double2* C() { return TFH_D_C; }
+    __device__ static const double2* CM1() { return TFH_D_CM1; }
+    __device__ static const double2* S() { return TFH_D_S; }
+    __device__ static const double2* LOG() { return TFH_D_LOG; }
+    __device__ static const double* INVC() { return TFH_D_LOG_INVC; }
+};
+template <> struct G<float> {
+    __device__ static const float2* E() { return TFH_F_E; }
+    __device__ static const int* EK() { return TFH_F_EK; }
+    __device__ static const float2* C() { return TFH_F_C; }
+    __device__ static const float2* CM1() { return TFH_F_CM1; }
+    __device__ static const float2* S() { return TFH_F_S; }
+    __device__ static const float2* LOG() { return TFH_F_LOG; }
+    __device__ static const float* INVC() { return TFH_F_LOG_INVC; }
+};
+
+template <class T, class U>
+__device__ __forceinline__ void stage(U* dst, const U* src, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
+}
+
+// LDS image of the tables one kernel needs.
+template <class T, bool EXP, bool PEXP0, bool PM1, bool LOG> struct Lds {
+    using V2 = typename P<T>::V2;
+    V2 S[EXP ? 32 : 1];
+    V2 E[PEXP0 ? P<T>::E_CNT : 1];
+    int EK[PEXP0 ? P<T>::E_CNT : 1];
+    V2 C[PEXP0 ? P<T>::C_CNT : 1];
+    V2 CM1[PM1 ? P<T>::CM1_CNT : 1];
+    V2 LG[LOG ? 128 : 1];
+    T INVC[LOG ? 128 : 1];
+
+    __device__ void load() {
+        if (EXP) stage<T>(S, G<T>::S(), 32);
+        if (PEXP0) {
+            stage<T>(E, G<T>::E(), P<T>::E_CNT);
+            stage<T>(EK, G<T>::EK(), P<T>::E_CNT);
+            stage<T>(C, G<T>::C(), P<T>::C_CNT);
+        }
+        if (PM1) stage<T>(CM1, G<T>::CM1(), P<T>::CM1_CNT);
+        if (LOG) {
+            stage<T>(LG, G<T>::LOG(), 128);
+            stage<T>(INVC, G<T>::INVC(), 128);
+        }
+    }
+    __device__ ExpTab<T> et() const { return {S}; }
+    // Without the pexp0 tables in LDS (texpm1, which needs them only for its
+    // rare |x0| > ln 2 lanes) they are read from global memory (L1/L2 hits).
+    __device__ Pexp0Tab<T> pt() const {
+        if constexpr (PEXP0) return {E, EK, C};
+        else return {G<T>::E(), G<T>::EK(), G<T>::C()};
+    }
+    __device__ Pm1Tab<T> mt() const { return {CM1}; }
+    __device__ LogTab<T> lt() const { return {INVC, LG}; }
+};
+
+template <class T, int FN> struct LdsFor;
+template <class T> struct LdsFor<T, FN_TEXP> { using type = Lds<T, true, true, false, false>; };
+template <class T> struct LdsFor<T, FN_TEXPM1> { using type = Lds<T, true, false, true, false>; };
+template <class T> struct LdsFor<T, FN_TLOG> { using type = Lds<T, false, false, true, true>; };
+template <class T> struct LdsFor<T, FN_TLOG1P> { using type = Lds<T, false, false, true, true>; };
+
+// Argument used for lanes past the end of the array: inside the main range of
+// every function, so tail lanes never pull a wave onto a slow path.
+template <class T> __device__ __forceinline__ T pad_arg() { return T(0.5); }
+
+// EPT consecutive elements of one thread.
+template <class T, int EPT> struct Vec { T v[EPT]; };
+
+// 16-byte vector load/store of a thread's EPT consecutive elements (the
+// pointer is 16-byte aligned: the host checks the base pointers).  Built with
+// -DTF_NONTEMPORAL=1 the streams use non-temporal accesses (no reuse).
+#ifndef TF_NONTEMPORAL
+#define TF_NONTEMPORAL 0
+#endif
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T, int EPT> __device__ __forceinline__ void vload(Vec<T, EPT>& r, const T* p) {
+    if constexpr ((sizeof(T) * EPT) % 16 == 0) {
+        constexpr int Q = sizeof(T) * EPT / 16, PER = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const u32x4* src = reinterpret_cast<const u32x4*>(p) + k;
+            u32x4 q = TF_NONTEMPORAL ? __builtin_nontemporal_load(src) : *src;
+            __builtin_memcpy(&r.v[k * PER], &q, 16);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) r.v[e] = p[e];
+    }
+}
+template <class T, int EPT> __device__ __forceinline__ void vstore(T* p, const Vec<T, EPT>& r) {
+    if constexpr ((sizeof(T) * EPT) % 16 == 0) {
+        constexpr int Q = sizeof(T) * EPT / 16, PER = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            u32x4 q;
+            __builtin_memcpy(&q, &r.v[k * PER], 16);
+            u32x4* dst = reinterpret_cast<u32x4*>(p) + k;
+            if (TF_NONTEMPORAL) __builtin_nontemporal_store(q, dst);
+            else *dst = q;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) p[e] = r.v[e];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Host side
+// ----------------------------------------------------------------------------
+// Compute units of the current device (cached per device).
+tf_status device_cus(int* cus);
+
+// Launch configuration per (function, format): elements per thread,
+// workgroups per compute unit (0 = as many as fit, from the occupancy API) and
+// prefetch depth.
+struct LaunchCfg { int ept; int bpc; int pd; };
+
+// The current configuration of twofold function fn (0..3) in format dtype.
+LaunchCfg twofold_launch_config(int fn, int dtype);
+
+template <class K> inline int blocks_per_cu(K kernel) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kBlock, 0) != hipSuccess ||
+        b <= 0) {
+        (void)hipGetLastError();
+        b = 2;
+    }
+    return b;
+}
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace tfk

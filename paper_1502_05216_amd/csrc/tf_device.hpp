@@ -489,12 +489,22 @@ __device__ __forceinline__ bool texpm1_small_fast(T x0, T x1, ExpTab<T> et, Pm1T
 
 // Newton step shared by plog and plog1p: r0 = log1p(a0 + a1), s = pexpm10(-r0),
 // u = ((a s) + a) + s, r1 = u0 + u1.  FAST: a0 + a1 finite.
+// The correction for a given seed r0 ~ log(1 + a).  The reductions keep
+// |r0| <= ln 2; in the general form a seed beyond the small range of pexpm10
+// (|r0| > 89/128 or NaN: an argument that is not coupled, or not finite, where
+// a coupled one is due) gives a NaN correction.  FAST: |r0| <= 89/128.
 template <bool FAST, class T>
-__device__ __forceinline__ Tw<T> plog_newton(Tw<T> a, LogTab<T> lt, Pm1Tab<T> mt) {
-    T r0 = log1p_1x<FAST>(a.x0 + a.x1, lt);
+__device__ __forceinline__ Tw<T> newton_seeded(Tw<T> a, T r0, Pm1Tab<T> mt) {
     Tw<T> s = pexpm10_small<FAST>(-r0, mt);
     Tw<T> u = add_tt(add_tt(mul_tt(a, s), a), s);
-    return {r0, u.x0 + u.x1};
+    T r1 = u.x0 + u.x1;
+    if constexpr (!FAST) r1 = (fabs_(r0) <= T(0.6953125)) ? r1 : P<T>::qnan();
+    return {r0, r1};
+}
+
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog_newton(Tw<T> a, LogTab<T> lt, Pm1Tab<T> mt) {
+    return newton_seeded<FAST>(a, log1p_1x<FAST>(a.x0 + a.x1, lt), mt);
 }
 
 template <class T> __device__ __forceinline__ Tw<T> add_n_ln2(Tw<T> X, int n) {
@@ -566,6 +576,229 @@ __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> 
         x1 = isnan_(v.x0) ? K::qnan() : x1;
         x1o = special_rule(x0, x1);
     }
+}
+
+// ----------------------------------------------------------------------------
+// The other entry points of the paper's interface: functions of a dotted
+// argument x0 (x1 = 0) and of a coupled argument (x0 + x1 rounds to x0), and
+// the p-functions, whose results are renormalised fast to a coupled twofold.
+// Same operation sequences as the oracle; general forms handle any argument,
+// FAST forms the arguments of the *_fast_arg predicates below.
+// ----------------------------------------------------------------------------
+
+// Renormalize fast a result, then the rule for a non-finite main part.
+template <class T> __device__ __forceinline__ void renorm_out(T z0, T z1, T& z0o, T& z1o) {
+    const bool fin = !(isnan_(z0) || fabs_(z0) == P<T>::INF);
+    Tw<T> r = fast_two_sum(z0, z1);
+    T o0 = fin ? r.x0 : z0;
+    T o1 = fin ? r.x1 : z1;
+    z0o = o0;
+    z1o = special_rule(o0, o1);
+}
+
+// pexp0 as a coupled p-function: 0 below the range, z0 = z1 = +inf above it
+// (as the paper writes it), else E (C T) scaled and renormalised fast.
+template <bool FAST, class T>
+__device__ __forceinline__ void pexp0_p(T x, Pexp0Tab<T> pt, T& z0o, T& z1o) {
+    using K = P<T>;
+    if constexpr (FAST) {
+        Scaled<T> s = pexp0_core<true>(x, pt);
+        Tw<T> r = fast_two_sum(fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k));
+        z0o = r.x0;
+        z1o = r.x1;
+    } else {
+        const bool in = x >= K::EXP_XLO && x <= K::EXP_XMAX;
+        Scaled<T> s = pexp0_core<false>(in ? x : T(0), pt);
+        Tw<T> r = fast_two_sum(fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k));
+        r = sel(x < K::EXP_XLO, Tw<T>{T(0), T(0)}, r);
+        r = sel(x > K::EXP_XMAX, Tw<T>{K::INF, K::INF}, r);
+        r = sel(isnan_(x), Tw<T>{x, x}, r);
+        z0o = r.x0;
+        z1o = r.x1;
+    }
+}
+
+// texp0 (dotted argument): z0 = exp(x0), z1 = (v0 - z0) + v1 with
+// v = pexp0(x0), in pexp0's 2^-k domain.  FAST: EXP_XLO <= x0 <= EXP_XMAX.
+template <bool FAST, class T>
+__device__ __forceinline__ void texp0_elem(T x0, ExpTab<T> et, Pexp0Tab<T> pt, T& z0o, T& z1o) {
+    using K = P<T>;
+    if constexpr (FAST) {
+        T z0 = exp1x<true>(x0, et);
+        Scaled<T> s = pexp0_core<true>(x0, pt);
+        T z0s = fldexp(z0, -s.k);                     // exact
+        z0o = z0;
+        z1o = fldexp((s.v.x0 - z0s) + s.v.x1, s.k);
+    } else {
+        T z0 = exp1x<false>(x0, et);
+        bool in = x0 >= K::EXP_XLO;                   // below: pexp0 gives (0, 0)
+        T xc = in ? x0 : K::EXP_XLO;
+        xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
+        Scaled<T> s = pexp0_core<false>(xc, pt);
+        T v0 = in ? s.v.x0 : T(0);
+        T v1 = in ? s.v.x1 : T(0);
+        int k = in ? s.k : 0;
+        T z0s = fldexp(z0, -k);                       // exact
+        z0o = z0;
+        z1o = special_rule(z0, fldexp((v0 - z0s) + v1, k));
+    }
+}
+
+// pexpm10 body (not renormalised), any argument: the small path for
+// |x| <= ln 2, pexp0(x) - 1 on the waves holding a larger in-range lane, -1
+// below the range.
+template <class T>
+__device__ __forceinline__ Tw<T> pexpm10_any(T x, Pexp0Tab<T> pt, Pm1Tab<T> mt) {
+    using K = P<T>;
+    bool small = fabs_(x) <= K::LN2_HI;
+    Tw<T> w = pexpm10_small<false>(small ? x : T(0), mt);
+    bool big = !small && x >= K::EXP_XLO && x <= K::EXP_XMAX;
+    if (__any(big)) {
+        T xc = big ? x : T(1);
+        Scaled<T> s = pexp0_core<false>(xc, pt);
+        Tw<T> wl = add_td(Tw<T>{fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k)}, T(-1));
+        w = sel(big, wl, w);
+    }
+    return sel(x < K::EXP_XLO, Tw<T>{T(-1), T(0)}, w);
+}
+
+// pexpm10 as a coupled p-function; texpm10: z0 = expm1(x0),
+// z1 = (w0 - z0) + w1.  FAST (both): |x0| <= ln 2.
+template <bool FAST, class T>
+__device__ __forceinline__ void pexpm10_p(T x, Pexp0Tab<T> pt, Pm1Tab<T> mt, T& z0o, T& z1o) {
+    using K = P<T>;
+    if constexpr (FAST) {
+        Tw<T> w = pexpm10_small<true>(x, mt);
+        Tw<T> r = fast_two_sum(w.x0, w.x1);
+        z0o = r.x0;
+        z1o = r.x1;
+    } else {
+        Tw<T> w = pexpm10_any(x, pt, mt);
+        Tw<T> r = fast_two_sum(w.x0, w.x1);
+        r = sel(x > K::EXP_XMAX, Tw<T>{K::INF, K::INF}, r);
+        r = sel(isnan_(x), Tw<T>{x, x}, r);
+        z0o = r.x0;
+        z1o = r.x1;
+    }
+}
+template <bool FAST, class T>
+__device__ __forceinline__ void texpm10_elem(T x0, ExpTab<T> et, Pexp0Tab<T> pt, Pm1Tab<T> mt,
+                                             T& z0o, T& z1o) {
+    if constexpr (FAST) {
+        T z0 = expm1_1x<true>(x0, et);
+        Tw<T> w = pexpm10_small<true>(x0, mt);
+        z0o = z0;
+        z1o = (w.x0 - z0) + w.x1;
+    } else {
+        T z0 = expm1_1x<false>(x0, et);
+        Tw<T> w = pexpm10_any(x0, pt, mt);
+        z0o = z0;
+        z1o = special_rule(z0, (w.x0 - z0) + w.x1);
+    }
+}
+
+// plog0 core (dotted y0 in (0, inf), not renormalised): y0 = 2^n z0, seed the
+// 1x log of z0, Newton correction with 1 + a = z0, + n ln2.
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog0_core(T y0, LogTab<T> lt, Pm1Tab<T> mt) {
+    int n;
+    Tw<T> z = log_scale(Tw<T>{y0, T(0)}, n);
+    Tw<T> a = {z.x0 - T(1), z.x1};                    // exact
+    return add_n_ln2(newton_seeded<FAST>(a, log1x<FAST>(z.x0, lt), mt), n);
+}
+
+// plog core (coupled y, y0 in (0, inf), not renormalised): scale by the
+// exponent of y0, a = (z0 - 1) + z1, Newton step, + n ln2.
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog_coupled_core(Tw<T> y, LogTab<T> lt, Pm1Tab<T> mt) {
+    int n;
+    Tw<T> z = log_scale(y, n);
+    Tw<T> a = {z.x0 - T(1), z.x1};
+    return add_n_ln2(plog_newton<FAST>(a, lt, mt), n);
+}
+
+// plog1p0 core (dotted y0 in (-1, inf), not renormalised): outside [-1/2, 1]
+// the plog of the renormalised 1 + y0, inside the Newton correction with
+// a = y0 seeded with log1p(y0).  One Newton step per lane: the branch only
+// selects its argument and seed.
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog1p0_core(T y0, LogTab<T> lt, Pm1Tab<T> mt) {
+    const bool outer = y0 < T(-0.5) || y0 > T(1);
+    int n;
+    Tw<T> z = log_scale(two_sum(T(1), y0), n);
+    Tw<T> a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, Tw<T>{y0, T(0)});
+    T r0 = log1p_1x<FAST>(outer ? a.x0 + a.x1 : y0, lt);
+    Tw<T> X = newton_seeded<FAST>(a, r0, mt);
+    return sel(outer, add_n_ln2(X, outer ? n : 0), X);
+}
+
+// plog1p core (coupled y, y0 in (-1, inf), not renormalised): outside
+// [-1/2, 1] the plog of the renormalised 1 + y, inside the Newton step on
+// a = y seeded with log1p(y0 + y1).
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog1p_core(Tw<T> y, LogTab<T> lt, Pm1Tab<T> mt) {
+    const bool outer = y.x0 < T(-0.5) || y.x0 > T(1);
+    Tw<T> a = y;
+    int n = 0;
+    const bool any_outer = __any(outer);
+    if (any_outer) {
+        Tw<T> w = add_td(y, T(1));
+        Tw<T> z = log_scale(two_sum(w.x0, w.x1), n);
+        a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, y);
+    }
+    Tw<T> X = plog_newton<FAST>(a, lt, mt);
+    if (any_outer) X = sel(outer, add_n_ln2(X, outer ? n : 0), X);
+    return X;
+}
+
+// The four log-family functions of each kind.  P: p-function (renormalised
+// result; main part outside the 1x domain -> the 1x value and the rule).
+// Otherwise t-function: x0 = the 1x function of y0, x1 = X1 + (X0 - x0).
+// FAST: y0 inside the 1x domain and, for a coupled argument, |y1| <= 2^-24 |y0|
+// (then every seed is within the small range of pexpm10).
+enum LogKind : int { LK_LOG0 = 0, LK_LOG1P0 = 1, LK_LOGC = 2, LK_LOG1PC = 3 };
+
+template <int KIND, bool PFN, bool FAST, class T>
+__device__ __forceinline__ void log_iface_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o,
+                                               T& x1o) {
+    using K = P<T>;
+    constexpr bool LP = KIND == LK_LOG1P0 || KIND == LK_LOG1PC;
+    Tw<T> X;
+    if constexpr (KIND == LK_LOG0) X = plog0_core<FAST>(y0, lt, mt);
+    else if constexpr (KIND == LK_LOG1P0) X = plog1p0_core<FAST>(y0, lt, mt);
+    else if constexpr (KIND == LK_LOGC) X = plog_coupled_core<FAST>(Tw<T>{y0, y1}, lt, mt);
+    else X = plog1p_core<FAST>(Tw<T>{y0, y1}, lt, mt);
+    if constexpr (PFN) {
+        if constexpr (FAST) {
+            Tw<T> r = fast_two_sum(X.x0, X.x1);
+            x0o = r.x0;
+            x1o = special_rule(r.x0, r.x1);
+        } else {
+            const bool valid = (LP ? y0 > T(-1) : y0 > T(0)) && y0 < K::INF;
+            T o0, o1;
+            renorm_out(X.x0, X.x1, o0, o1);
+            T e0 = LP ? log1p_1x<false>(y0, lt) : log1x<false>(y0, lt);
+            x0o = valid ? o0 : e0;
+            x1o = valid ? o1 : special_rule(e0, T(0));
+        }
+    } else {
+        T u0 = LP ? log1p_1x<FAST>(y0, lt) : log1x<FAST>(y0, lt);
+        T x1 = X.x1 + (X.x0 - u0);
+        x0o = u0;
+        x1o = FAST ? x1 : special_rule(u0, x1);
+    }
+}
+
+// For log1p of a coupled argument, y0 + y1 > -1 (rounded) also keeps 1 + y
+// positive, so its logarithm's reduction stays in range.
+template <int KIND, class T> __device__ __forceinline__ bool log_iface_fast_arg(T y0, T y1) {
+    constexpr T REL = T(1.0 / 16777216.0);            // 2^-24
+    if constexpr (KIND == LK_LOG0) return y0 > T(0) && y0 < P<T>::INF;
+    else if constexpr (KIND == LK_LOG1P0) return y0 > T(-1) && y0 < P<T>::INF;
+    else if constexpr (KIND == LK_LOGC)
+        return y0 > T(0) && y0 < P<T>::INF && fabs_(y1) <= y0 * REL;
+    else
+        return y0 > T(-1) && y0 < P<T>::INF && y0 + y1 > T(-1) && fabs_(y1) <= fabs_(y0) * REL;
 }
 
 // ----------------------------------------------------------------------------

@@ -126,3 +126,29 @@ def test_batch_plan_validation(lib):
     assert L.tf_batch_launch(None, None) == 1
     assert L.tf_batch_plan_destroy(None) == 1
     assert L.tf_batch_plan_info(None, None, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tf_" + n + s for n in ("pexp0", "texp0", "pexpm10", "texpm10",
+                                                         "plog0", "tlog0", "plog1p0", "tlog1p0")
+                                  for s in ("", "f")])
+def test_dotted_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, None, 0, None) == 0
+    fake = ctypes.c_void_p(0x1000)
+    for k in range(3):
+        args = [fake] * 3
+        args[k] = None
+        assert fn(*args, 10, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tf_" + n + s for n in ("texpp", "pexp", "texpm1p", "pexpm1",
+                                                         "tlogp", "plog", "tlog1pp", "plog1p")
+                                  for s in ("", "f")])
+def test_coupled_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, None, None, 0, None) == 0
+    fake = ctypes.c_void_p(0x1000)
+    for k in range(4):
+        args = [fake] * 4
+        args[k] = None
+        assert fn(*args, 10, None) == 1
