@@ -11,11 +11,11 @@ the roofline of the dominant kernel (algorithmic FP64 flops from the oracle's
 counting build, tests/golden/opcounts.json, over the measured kernel time);
 the batched launch over 4096 ragged arrays of mixed function and format
 against the per-array launches and the mix-weighted plain rate; the forward
-and backward chain tlog1p(texpm1(texp(x))) at 2^24; and the CPU oracle timed
-on the host cores.
+and backward chain tlog1p(texpm1(texp(x))) at 2^24; the other entry points of
+the paper's interface at 2^26; and the CPU oracle timed on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f32]
-                    [--no-batch] [--no-chain]
+                    [--no-batch] [--no-chain] [--no-interface]
 """
 import argparse
 import json
@@ -155,6 +155,41 @@ def bench_batch(tf, workloads, per64, per32, reps):
             "vs_mix_weighted_plain": None if mix_ms is None else mix_ms / ms}
 
 
+def bench_interface(tf, workloads, opc, reps, dtypes):
+    """The other entry points of the paper's interface on 2^26 elements each
+    (dotted argument: x0 -> z0, z1, 24 B per binary64 element; coupled
+    argument: 32 B)."""
+    import torch
+    dev = torch.device("cuda:0")
+    res = {}
+    for key, dt in (("f64", np.float64), ("f32", np.float32)):
+        if key not in dtypes:
+            continue
+        res[key] = {}
+        for name in workloads.DOTTED + workloads.COUPLED:
+            dotted = name in workloads.DOTTED
+            a, b = workloads.twofold_inputs(name, N, dt, coupled=not dotted)
+            x0 = torch.from_numpy(a).to(dev)
+            x1 = None if dotted else torch.from_numpy(b).to(dev)
+            out = (torch.empty_like(x0), torch.empty_like(x0))
+            if dotted:
+                ms = kernel_ms(lambda: getattr(tf, name)(x0, out=out), (), reps)
+            else:
+                ms = kernel_ms(lambda: getattr(tf, name)(x0, x1, out=out), (), reps)
+            isz = 8 if key == "f64" else 4
+            nbytes = (3 if dotted else 4) * isz
+            c = opc[key][name]
+            res[key][name] = {"ms": ms, "gelem_s": N / ms / 1e6,
+                              "hbm_gbs": N * nbytes / ms / 1e6, "bytes_per_elem": nbytes,
+                              "tflops": N * c["flops"] / ms / 1e9,
+                              "issue_frac": N * c["ops"] / (ms * 1e-3) / (PEAK_FP64_ISSUE_T * 1e12),
+                              "traffic": traffic_for("%s_%s" % (key, name), N)}
+            log("%s %-8s %.3f ms  %.1f Gelem/s" % (key, name, ms, res[key][name]["gelem_s"]))
+            del x0, x1, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_chain(tf, workloads, reps):
     """Forward and backward of y = tlog1p(texpm1(texp(x))) on 2^24 binary64
     twofolds: three forward and three backward launches per pass."""
@@ -188,6 +223,8 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 rates")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched launch")
     ap.add_argument("--no-chain", action="store_true", help="skip the forward+backward chain")
+    ap.add_argument("--no-interface", action="store_true",
+                    help="skip the other entry points of the interface")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU oracle time (whole passes over the step)")
     ap.add_argument("--cpu-core-sample", type=int, default=1 << 21)
@@ -296,6 +333,11 @@ def main():
         chain = bench_chain(tf, workloads, 10)
         log("chain %.3f ms  %.1f Gelem/s" % (chain["ms"], chain["gelem_s"]))
 
+    iface = None
+    if not args.no_interface:
+        log("other interface functions, 2^26 each")
+        iface = bench_interface(tf, workloads, opc, 10, ("f64",) if args.no_f32 else ("f64", "f32"))
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: oracle, at least %.0f s" % args.cpu_seconds)
@@ -317,6 +359,7 @@ def main():
         "per_function_f32": per32,
         "batched": batch,
         "fwd_bwd_chain": chain,
+        "interface": iface,
         "src_hash": src_hash(),
     }
     print(json.dumps(rec), flush=True)

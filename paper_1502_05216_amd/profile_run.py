@@ -19,7 +19,9 @@ def main():
     ap.add_argument("--dtype", default="f64", help="f64, f32 or f64,f32")
     ap.add_argument("--n", type=int, default=1 << 26)
     ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--fn", default="all")
+    ap.add_argument("--fn", default="all",
+                    help="comma-separated names; 'all' = the four twofold functions, "
+                         "'iface' = the other 16 interface functions, 'everything' = both")
     args = ap.parse_args()
 
     import torch
@@ -33,17 +35,27 @@ def main():
     torch.cuda.synchronize()
     print("copy of %d x %d bytes done" % (args.n, src.element_size()), flush=True)
     del src, dst
-    funcs = tf.TWOFOLD if args.fn == "all" else tuple(args.fn.split(","))
+    if args.fn == "all":
+        funcs = tf.TWOFOLD
+    elif args.fn == "iface":
+        funcs = tf.DOTTED + tf.COUPLED
+    elif args.fn == "everything":
+        funcs = tf.TWOFOLD + tf.DOTTED + tf.COUPLED
+    else:
+        funcs = tuple(args.fn.split(","))
     for dname in args.dtype.split(","):
         dt = {"f64": np.float64, "f32": np.float32}[dname]
         for fn in funcs:
-            a, b = workloads.twofold_inputs(fn, args.n, dt)
+            a, b = workloads.twofold_inputs(fn, args.n, dt, coupled=fn in tf.COUPLED)
             x0 = torch.from_numpy(a).to(dev)
             x1 = torch.from_numpy(b).to(dev)
             z0 = torch.empty_like(x0)
             z1 = torch.empty_like(x0)
             for _ in range(args.reps):
-                getattr(tf, fn)(x0, x1, out=(z0, z1))
+                if fn in tf.DOTTED:
+                    getattr(tf, fn)(x0, out=(z0, z1))
+                else:
+                    getattr(tf, fn)(x0, x1, out=(z0, z1))
             torch.cuda.synchronize()
             print("%s %s x%d done" % (fn, dname, args.reps), flush=True)
             del x0, x1, z0, z1

@@ -27,6 +27,8 @@ from collections import defaultdict
 from ._build import source_hash
 
 FN_NAMES = {0: "texp", 1: "texpm1", 2: "tlog", 3: "tlog1p"}
+IFACE_NAMES = ["pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0",
+               "pexp", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p"]
 
 
 def short_name(kernel):
@@ -35,6 +37,9 @@ def short_name(kernel):
     if m:
         return "k_twofold<%s,%s> ept%s pd%s" % (m.group(1), FN_NAMES[int(m.group(2))],
                                                 m.group(3), m.group(4))
+    m = re.search(r"k_iface<(double|float), (\d+), (\d+)>", kernel)
+    if m:
+        return "k_iface<%s,%s> ept%s" % (m.group(1), IFACE_NAMES[int(m.group(2))], m.group(3))
     m = re.search(r"k_backward<(double|float), (\d), (\d+)>", kernel)
     if m:
         return "k_backward<%s,%s> ept%s" % (m.group(1), FN_NAMES[int(m.group(2))], m.group(3))
@@ -49,9 +54,12 @@ def short_name(kernel):
 
 def traffic_key(kernel):
     m = re.search(r"k_twofold<(double|float), (\d),", kernel)
-    if not m:
-        return None
-    return ("f64_" if m.group(1) == "double" else "f32_") + FN_NAMES[int(m.group(2))]
+    if m:
+        return ("f64_" if m.group(1) == "double" else "f32_") + FN_NAMES[int(m.group(2))]
+    m = re.search(r"k_iface<(double|float), (\d+),", kernel)
+    if m:
+        return ("f64_" if m.group(1) == "double" else "f32_") + IFACE_NAMES[int(m.group(2))]
+    return None
 
 
 def stats(args):
@@ -130,7 +138,7 @@ def traffic(args):
     out = {"src_hash": h, "n": args.n, "copy_bytes": copy_bytes,
            "copy_fetch_kib": cf[0], "copy_write_kib": cw[0],
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
-    lines = ["# HBM traffic per launch of k_twofold, 2^26 elements (MI355X)", "",
+    lines = ["# HBM traffic per launch of the streaming kernels, 2^26 elements (MI355X)", "",
              "Counter runs (from the repository root; one counter per run):", "",
              "    " + args.command_fetch, "    " + args.command_write, "",
              "Source hash of paper_1502_05216_amd/csrc: %s" % h, "",
@@ -146,7 +154,8 @@ def traffic(args):
         fk = sum(fetch[k]) / len(fetch[k])
         wk = sum(write[k]) / len(write[k])
         b = fk * 1024 * f_scale + wk * 1024 * w_scale
-        alg = args.n * (32 if key.startswith("f64") else 16)
+        nb = 3 if key.split("_", 1)[1] in IFACE_NAMES[:8] else 4
+        alg = args.n * nb * (8 if key.startswith("f64") else 4)
         out["kernels"][key] = {"src_hash": h, "n": args.n, "bytes_per_launch": b,
                                "algorithmic_bytes": alg, "fetch_kib": fk, "write_kib": wk,
                                "dispatches": len(fetch[k])}

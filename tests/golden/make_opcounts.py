@@ -4,7 +4,9 @@ benchmark workloads -- the "algorithmic flops" of the roofline.
 
 add counts + and -, mul counts *, fma counts fused multiply-adds (2 flops),
 other counts rint/ldexp/frexp/divide.  Sample: the first 2^18 elements of the
-2^26-element benchmark arrays of each function (binary64 and binary32).
+2^26-element benchmark arrays of each function (binary64 and binary32): the
+four twofold functions and the other entry points of the interface (coupled
+arguments for the coupled-argument functions; x0 alone for the dotted ones).
 
 Run:  python tests/golden/make_opcounts.py
 """
@@ -27,9 +29,12 @@ def main():
     out = {"sample": "first 2^18 of workloads.twofold_inputs(fn, 2^26, dtype)", "f64": {},
            "f32": {}}
     for key, dt, sfx in (("f64", np.float64, ""), ("f32", np.float32, "f")):
-        for fn in workloads.FUNCS:
-            x0, x1 = workloads.twofold_inputs(fn, 1 << 26, dt)
-            c = oracle.op_count(fn + sfx, x0[:SAMPLE], x1[:SAMPLE])
+        for fn in workloads.FUNCS + workloads.DOTTED + workloads.COUPLED:
+            x0, x1 = workloads.twofold_inputs(fn, 1 << 26, dt, coupled=fn in workloads.COUPLED)
+            if fn in workloads.DOTTED:
+                c = oracle.op_count(fn + sfx, x0[:SAMPLE])
+            else:
+                c = oracle.op_count(fn + sfx, x0[:SAMPLE], x1[:SAMPLE])
             n = float(c["n"])
             rec = {k: c[k] / n for k in ("add", "mul", "fma", "other")}
             rec["ops"] = rec["add"] + rec["mul"] + rec["fma"]
