@@ -11,6 +11,8 @@ into oracle/libtfo.so) with numpy-array functions:
                                         # texpm10 plog0 tlog0 plog1p0 tlog1p0 (+ f)
     z0, z1 = oracle.pexp(x0, x1)        # coupled argument: texpp pexp texpm1p
                                         # pexpm1 tlogp plog tlog1pp plog1p (+ f)
+    z0, z1 = oracle.tadd(x0, x1, y0, y1)   # twofold arithmetic: tadd tsub tmul
+    z0, z1 = oracle.tsqrt(x0, x1)          # tdiv (+ f), tsqrt (+ f)
     gx0, gx1 = oracle.texp_bwd(s0, s1, g0, g1)
     counts = oracle.op_count("texp", x0, x1)   # {add, mul, fma, other, n}
 
@@ -36,6 +38,8 @@ FUNCS_1X = ["exp1x", "expm1_1x", "log1x", "log1p_1x"]
 # the other entry points of the paper's interface
 FUNCS_D = ["pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0"]
 FUNCS_C = ["texpp", "pexp", "texpm1p", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p"]
+# twofold arithmetic: binary operations on (x0, x1, y0, y1), and tsqrt(x0, x1)
+FUNCS_ARITH = ["tadd", "tsub", "tmul", "tdiv"]
 
 
 def build(verbose=False):
@@ -87,6 +91,13 @@ def _load(path=None):
         for sfx in ("", "f"):
             getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, P, S, I]
             getattr(lib, "tfo_count_%s%s_n" % (base, sfx)).argtypes = [P, S, P]
+    for base in FUNCS_ARITH:
+        for sfx in ("", "f"):
+            getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, P, P, P, P, S, I]
+            getattr(lib, "tfo_count_%s%s_n" % (base, sfx)).argtypes = [P, P, P, P, S, P]
+    for sfx in ("", "f"):
+        getattr(lib, "tfo_tsqrt%s_n" % sfx).argtypes = [P, P, P, P, S, I]
+        getattr(lib, "tfo_count_tsqrt%s_n" % sfx).argtypes = [P, P, S, P]
     lib.tfo_eft_n.argtypes = [I, P, P, P, P, S]
     _libs[path] = lib
     return lib
@@ -173,6 +184,11 @@ def _bind(ns, path=None):
     for b in FUNCS_D:
         ns[b] = _mk_d(b, np.float64, path)
         ns[b + "f"] = _mk_d(b + "f", np.float32, path)
+    for b in FUNCS_ARITH:      # same array shape as the backward: 4 in, 2 out
+        ns[b] = _mk_bwd(b, np.float64, path)
+        ns[b + "f"] = _mk_bwd(b + "f", np.float32, path)
+    ns["tsqrt"] = _mk_tw("tsqrt", np.float64, path)
+    ns["tsqrtf"] = _mk_tw("tsqrtf", np.float32, path)
 
 
 _bind(globals())

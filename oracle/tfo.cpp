@@ -59,6 +59,7 @@ template <class U> Cnt<U> rint(Cnt<U> a) { g_cnt.other++; return Cnt<U>(std::rin
 template <class U> Cnt<U> ldexp(Cnt<U> a, int k) { g_cnt.other++; return Cnt<U>(std::ldexp(a.v, k)); }
 template <class U> Cnt<U> frexp(Cnt<U> a, int* e) { g_cnt.other++; return Cnt<U>(std::frexp(a.v, e)); }
 template <class U> Cnt<U> fabs(Cnt<U> a) { return Cnt<U>(std::fabs(a.v)); }
+template <class U> Cnt<U> sqrt(Cnt<U> a) { g_cnt.other++; return Cnt<U>(std::sqrt(a.v)); }
 template <class U> bool isnan(Cnt<U> a) { return std::isnan(a.v); }
 template <class U> bool isinf(Cnt<U> a) { return std::isinf(a.v); }
 
@@ -69,6 +70,7 @@ using std::isinf;
 using std::isnan;
 using std::ldexp;
 using std::rint;
+using std::sqrt;
 
 template <class T> struct Base { using type = T; };
 template <class U> struct Base<Cnt<U>> { using type = U; };
@@ -767,6 +769,50 @@ template <class T> T tlog1pp(T y0, T y1, T* x1out) {
     return u0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Twofold arithmetic over arrays (the paper's second measured workload,      */
+/* section "Twofolds update", table of tadd/tmul/tdiv/tsqrt with FMA):        */
+/* z = x op y for twofolds x = x0 + x1, y = y0 + y1.  The main part is the    */
+/* 1x operation on the main parts; z1 carries the twofold error term.  The    */
+/* definitions are those of the twofold primitives above; subtraction is the  */
+/* corrected Algorithm 2.2 of section "Twofold bugs" as printed (for a - b).  */
+/* After the operation, the rule for a non-finite main part.                  */
+/* ------------------------------------------------------------------------ */
+template <class T> Tw<T> two_diff(T a, T b) {
+    T d = a - b;
+    T bp = d - a;
+    T ap = d - bp;
+    T bs = b + bp;
+    T as = a - ap;
+    return {d, as - bs};
+}
+
+template <class T> Tw<T> rule_tw(Tw<T> z) { return {z.x0, special_rule(z.x0, z.x1)}; }
+
+template <class T> Tw<T> tadd(Tw<T> x, Tw<T> y) { return rule_tw(add_tt(x, y)); }
+template <class T> Tw<T> tsub(Tw<T> x, Tw<T> y) {
+    Tw<T> dt = two_diff(x.x0, y.x0);
+    return rule_tw(Tw<T>{dt.x0, dt.x1 + (x.x1 - y.x1)});
+}
+template <class T> Tw<T> tmul(Tw<T> x, Tw<T> y) { return rule_tw(mul_tt(x, y)); }
+template <class T> Tw<T> tdiv(Tw<T> x, Tw<T> y) { return rule_tw(div_tt(x, y)); }
+/* sqrt with the FMA remainder r = fma(-q, q, x0) (section "Older CPUs" names
+ * this remainder for square roots): z0 = sqrt(x0), z1 = (r + x1) / (2 z0).
+ * At x0 = 0 the correction is taken as 0 (the linearisation has no term
+ * there). */
+template <class T> Tw<T> tsqrt_tw(Tw<T> x) {
+    T z0 = sqrt(x.x0);
+    T r = fma(-z0, z0, x.x0);
+    T z1 = (r + x.x1) / (z0 + z0);
+    if (x.x0 == T(0)) z1 = T(0);
+    return rule_tw(Tw<T>{z0, z1});
+}
+template <class T> T tsqrt(T x0, T x1, T* z1) {
+    Tw<T> r = tsqrt_tw(Tw<T>{x0, x1});
+    *z1 = r.x1;
+    return r.x0;
+}
+
 /* Backward (twofold adjoints, not in the paper): for x = x0 + x1 and the saved
  * forward value s (z for texp/texpm1, y for tlog/tlog1p), given the twofold
  * upstream gradient g:  texp g*z, texpm1 g*(z + 1), tlog g/y, tlog1p g/(1 + y). */
@@ -939,6 +985,19 @@ TFO_BWD(texpf_bwd, float, bwd_texp)
 TFO_BWD(texpm1f_bwd, float, bwd_texpm1)
 TFO_BWD(tlogf_bwd, float, bwd_tlog)
 TFO_BWD(tlog1pf_bwd, float, bwd_tlog1p)
+
+/* Twofold arithmetic: binary operations take (x0, x1, y0, y1). */
+#define TFO_ARITH(NAME, T, FN) TFO_BWD(NAME, T, FN)
+TFO_ARITH(tadd, double, tadd)
+TFO_ARITH(tsub, double, tsub)
+TFO_ARITH(tmul, double, tmul)
+TFO_ARITH(tdiv, double, tdiv)
+TFO_ARITH(taddf, float, tadd)
+TFO_ARITH(tsubf, float, tsub)
+TFO_ARITH(tmulf, float, tmul)
+TFO_ARITH(tdivf, float, tdiv)
+TFO_TW(tsqrt, double, tsqrt)
+TFO_TW(tsqrtf, float, tsqrt)
 
 /* Error-free transforms, exported for their exactness pins. */
 void tfo_eft_n(int which, const double* a, const double* b, double* s, double* t, size_t n) {

@@ -45,6 +45,10 @@ MUTANTS = {
     "texp0 dropped v1": ("z1 = ldexp((s.v.x0 - z0s) + s.v.x1, s.k);",
                          "z1 = ldexp((s.v.x0 - z0s), s.k);"),
     "p-function not renormalised": ("Tw<T> r = fast_two_sum(z0, z1);", "Tw<T> r = {z0, z1};"),
+    # twofold arithmetic
+    "two_diff sign": ("T bs = b + bp;", "T bs = b - bp;"),
+    "tdiv dropped y1": ("T q1 = ((r + A.x1) - q0 * B.x1) / B.x0;", "T q1 = (r + A.x1) / B.x0;"),
+    "tsqrt remainder sign": ("T r = fma(-z0, z0, x.x0);", "T r = fma(z0, z0, -x.x0);"),
     "plog1p outer 1 + y": ("Tw<T> w = add_td(y, T(1));\n        return plog_coupled_core",
                            "Tw<T> w = add_td(y, T(-1));\n        return plog_coupled_core"),
 }
@@ -80,6 +84,36 @@ def battery_interface(o):
     return True
 
 
+def battery_arith(o):
+    """Twofold arithmetic against exact rationals on a few hundred operands."""
+    from fractions import Fraction as F
+    rng = np.random.default_rng(4)
+    n = 300
+    x0 = np.exp2(rng.uniform(-20, 20, n)) * np.where(rng.uniform(-1, 1, n) < 0, -1, 1)
+    x1 = x0 * rng.uniform(-1, 1, n) * 2.0 ** -53
+    y0 = np.exp2(rng.uniform(-20, 20, n)) * np.where(rng.uniform(-1, 1, n) < 0, -1, 1)
+    y1 = y0 * rng.uniform(-1, 1, n) * 2.0 ** -53
+    y0[:50] = -x0[:50] * (1 + 2.0 ** -30)
+    y1[:50] = y0[:50] * rng.uniform(-1, 1, 50) * 2.0 ** -53
+    v = lambda a, b: F(float(a)) + F(float(b))
+    for op in ("tadd", "tsub", "tmul", "tdiv"):
+        z0, z1 = getattr(o, op)(x0, x1, y0, y1)
+        for a, b, c, d, r0, r1 in zip(x0, x1, y0, y1, z0, z1):
+            x, y = v(a, b), v(c, d)
+            ex = {"tadd": x + y, "tsub": x - y, "tmul": x * y, "tdiv": x / y}[op]
+            size = abs(F(float(a))) + abs(F(float(c))) if op in ("tadd", "tsub") else abs(ex)
+            if not np.isfinite(r1) or abs(v(r0, r1) - ex) > size * F(2) ** -100:
+                return False
+    xs = np.abs(x0)
+    xs1 = xs * rng.uniform(-1, 1, n) * 2.0 ** -53
+    z0, z1 = o.tsqrt(xs, xs1)
+    for a, b, r0, r1 in zip(xs, xs1, z0, z1):
+        z = v(r0, r1)
+        if not np.isfinite(r1) or abs(z * z - v(a, b)) > abs(F(float(a))) * F(2) ** -100:
+            return False
+    return True
+
+
 def battery(o):
     """True if the oracle build `o` passes a short version of the pins."""
     thr = {"texp": (-98, -95), "texpm1": (-98, -95), "tlog": (-98, -93), "tlog1p": (-98, -93)}
@@ -105,7 +139,7 @@ def battery(o):
                 if mpref.exact(fn, xi) is not None and abs(float(mpref.exact(fn, xi))) > 2.0 ** -1022]
         if max(errs) > 0.52 or np.mean(errs) > 0.3:
             return False
-    return battery_interface(o)
+    return battery_interface(o) and battery_arith(o)
 
 
 def test_unmodified_source_passes(tmp_path):
