@@ -12,10 +12,11 @@ counting build, tests/golden/opcounts.json, over the measured kernel time);
 the batched launch over 4096 ragged arrays of mixed function and format
 against the per-array launches and the mix-weighted plain rate; the forward
 and backward chain tlog1p(texpm1(texp(x))) at 2^24; the other entry points of
-the paper's interface at 2^26; and the CPU oracle timed on the host cores.
+the paper's interface at 2^26; the twofold arithmetic (tadd, tsub, tmul, tdiv,
+tsqrt) at 2^26; and the CPU oracle timed on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f32]
-                    [--no-batch] [--no-chain] [--no-interface]
+                    [--no-batch] [--no-chain] [--no-interface] [--no-arith]
 """
 import argparse
 import json
@@ -190,6 +191,45 @@ def bench_interface(tf, workloads, opc, reps, dtypes):
     return res
 
 
+def bench_arith(tf, reps, dtypes):
+    """Twofold arithmetic (tadd, tsub, tmul, tdiv, tsqrt) on 2^26 elements:
+    48 B per binary64 element for the binary operations, 32 B for tsqrt; all
+    are bound by HBM."""
+    import torch
+    dev = torch.device("cuda:0")
+    res = {}
+    rng = np.random.default_rng(1502052161)
+    for key, dt in (("f64", np.float64), ("f32", np.float32)):
+        if key not in dtypes:
+            continue
+        eps = dt(2.0 ** (-53 if key == "f64" else -24))
+        arrs = []
+        for _ in range(2):
+            a0 = (np.exp2(rng.uniform(-30, 30, N)) * np.where(rng.uniform(-1, 1, N) < 0, -1, 1)
+                  ).astype(dt)
+            arrs += [a0, ((a0 * rng.uniform(-1, 1, N).astype(dt)) * eps).astype(dt)]
+        x0, x1, y0, y1 = [torch.from_numpy(a).to(dev) for a in arrs]
+        ax0 = x0.abs()
+        out = (torch.empty_like(x0), torch.empty_like(x0))
+        res[key] = {}
+        isz = 8 if key == "f64" else 4
+        for op in ("tadd", "tsub", "tmul", "tdiv", "tsqrt"):
+            if op == "tsqrt":
+                ms = kernel_ms(lambda: tf.tsqrt(ax0, x1, out=out), (), reps)
+                nbytes = 4 * isz
+            else:
+                ms = kernel_ms(lambda: getattr(tf, op)(x0, x1, y0, y1, out=out), (), reps)
+                nbytes = 6 * isz
+            res[key][op] = {"ms": ms, "gelem_s": N / ms / 1e6, "bytes_per_elem": nbytes,
+                            "hbm_gbs": N * nbytes / ms / 1e6,
+                            "hbm_frac": N * nbytes / ms / 1e6 / PEAK_HBM_GBS}
+            log("%s %-6s %.3f ms  %.1f Gelem/s  %.0f GB/s" % (key, op, ms, res[key][op]["gelem_s"],
+                                                             res[key][op]["hbm_gbs"]))
+        del x0, x1, y0, y1, ax0, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_chain(tf, workloads, reps):
     """Forward and backward of y = tlog1p(texpm1(texp(x))) on 2^24 binary64
     twofolds: three forward and three backward launches per pass."""
@@ -225,6 +265,7 @@ def main():
     ap.add_argument("--no-chain", action="store_true", help="skip the forward+backward chain")
     ap.add_argument("--no-interface", action="store_true",
                     help="skip the other entry points of the interface")
+    ap.add_argument("--no-arith", action="store_true", help="skip the twofold arithmetic")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU oracle time (whole passes over the step)")
     ap.add_argument("--cpu-core-sample", type=int, default=1 << 21)
@@ -338,6 +379,11 @@ def main():
         log("other interface functions, 2^26 each")
         iface = bench_interface(tf, workloads, opc, 10, ("f64",) if args.no_f32 else ("f64", "f32"))
 
+    arith = None
+    if not args.no_arith:
+        log("twofold arithmetic, 2^26 each")
+        arith = bench_arith(tf, 10, ("f64",) if args.no_f32 else ("f64", "f32"))
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline: oracle, at least %.0f s" % args.cpu_seconds)
@@ -360,6 +406,7 @@ def main():
         "batched": batch,
         "fwd_bwd_chain": chain,
         "interface": iface,
+        "arith": arith,
         "src_hash": src_hash(),
     }
     print(json.dumps(rec), flush=True)

@@ -179,6 +179,40 @@ tf_status tf_tlog1ppf(const float* x0, const float* x1, float* z0, float* z1, si
 tf_status tf_plog1pf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
                      void* stream);
 
+/* --- twofold arithmetic ------------------------------------------------
+ * The paper's second measured workload (section "Twofolds update": tadd,
+ * tmul, tdiv, tsqrt with FMA).  z = x op y for twofolds x = x0 + x1,
+ * y = y0 + y1; the main part z0 is the 1x operation on the main parts
+ * (IEEE, correctly rounded), z1 the twofold error term:
+ *   tadd   (s, t) = two_sum(x0, y0),  z1 = t + (x1 + y1)
+ *   tsub   (d, t) = the corrected subtraction of section "Twofold bugs",
+ *          z1 = t + (x1 - y1)
+ *   tmul   z1 = fma(x0, y1, fma(x1, y0, e)),  e = fma(x0, y0, -z0)
+ *   tdiv   r = fma(-z0, y0, x0),  z1 = ((r + x1) - z0 y1) / y0
+ *   tsqrt  r = fma(-z0, z0, x0),  z1 = (r + x1) / (2 z0)  (0 when x0 = 0)
+ * Then the rule for non-finite main parts.  Arrays as above; tsqrt reads
+ * x0, x1 only. */
+tf_status tf_tadd(const double* x0, const double* x1, const double* y0, const double* y1,
+                  double* z0, double* z1, size_t n, void* stream);
+tf_status tf_tsub(const double* x0, const double* x1, const double* y0, const double* y1,
+                  double* z0, double* z1, size_t n, void* stream);
+tf_status tf_tmul(const double* x0, const double* x1, const double* y0, const double* y1,
+                  double* z0, double* z1, size_t n, void* stream);
+tf_status tf_tdiv(const double* x0, const double* x1, const double* y0, const double* y1,
+                  double* z0, double* z1, size_t n, void* stream);
+tf_status tf_tsqrt(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                   void* stream);
+tf_status tf_taddf(const float* x0, const float* x1, const float* y0, const float* y1, float* z0,
+                   float* z1, size_t n, void* stream);
+tf_status tf_tsubf(const float* x0, const float* x1, const float* y0, const float* y1, float* z0,
+                   float* z1, size_t n, void* stream);
+tf_status tf_tmulf(const float* x0, const float* x1, const float* y0, const float* y1, float* z0,
+                   float* z1, size_t n, void* stream);
+tf_status tf_tdivf(const float* x0, const float* x1, const float* y0, const float* y1, float* z0,
+                   float* z1, size_t n, void* stream);
+tf_status tf_tsqrtf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                    void* stream);
+
 /* --- backward (twofold adjoints; not part of the paper) ----------------
  * Gradient of a twofold function with respect to its twofold argument
  * x = x0 + x1, given the twofold upstream gradient g = g0 + g1 and the saved

@@ -13,6 +13,8 @@ GPU, in binary64 and binary32:
     z0, z1 = texpp(x0, x1), pexp(x0, x1), texpm1p(x0, x1), pexpm1(x0, x1),
              tlogp(y0, y1), plog(y0, y1), tlog1pp(y0, y1), plog1p(y0, y1)
                                                         # coupled argument
+    z0, z1 = tadd(x0, x1, y0, y1), tsub(...), tmul(...), tdiv(...), tsqrt(x0, x1)
+                                                        # twofold arithmetic
     gx0, gx1 = texp_bwd(z0, z1, g0, g1)                 # twofold adjoints
     autograd.TExp / TExpm1 / TLog / TLog1p              # torch.autograd.Function
 
@@ -20,8 +22,8 @@ Arguments are contiguous torch tensors on the GPU; work is enqueued on the
 current stream.  The kernels live in libtwofold_hip.so (csrc/, C ABI in
 include/twofold_hip.h); this package only marshals arguments.
 """
-from ._lib import (COUPLED, DOTTED, ONEX, TWOFOLD, TwofoldError, backward_call,
-                   declared_functions, dotted_call, lib, onex_call, twofold_call)
+from ._lib import (ARITH, COUPLED, DOTTED, ONEX, TWOFOLD, TwofoldError, arith_call,
+                   backward_call, declared_functions, dotted_call, lib, onex_call, twofold_call)
 
 
 def texp(x0, x1, out=None):
@@ -88,6 +90,21 @@ def _coupled(name):
     return f
 
 
+def _arith(name):
+    def f(x0, x1, y0, y1, out=None):
+        return arith_call(name, x0, x1, y0, y1, out)
+    f.__name__ = name
+    f.__doc__ = "z0, z1 = %s of the twofolds x0 + x1 and y0 + y1, elementwise" % name
+    return f
+
+
+def tsqrt(x0, x1, out=None):
+    """z0, z1 = sqrt(x0 + x1) elementwise (twofold square root)."""
+    return twofold_call("tsqrt", x0, x1, out)
+
+
+for _n in ARITH:
+    globals()[_n] = _arith(_n)
 for _n in DOTTED:
     globals()[_n] = _dotted(_n)
 for _n in COUPLED:
@@ -102,4 +119,4 @@ def build(verbose=False):
 __all__ = ["texp", "texpm1", "tlog", "tlog1p", "exp1x", "expm1_1x", "log1x", "log1p_1x",
            "texp_bwd", "texpm1_bwd", "tlog_bwd", "tlog1p_bwd",
            "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX",
-           "DOTTED", "COUPLED"] + list(DOTTED) + list(COUPLED)
+           "DOTTED", "COUPLED", "ARITH", "tsqrt"] + list(DOTTED) + list(COUPLED) + list(ARITH)

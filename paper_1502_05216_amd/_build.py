@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtwofold_hip.so")
-SOURCES = [os.path.join(PKG, "csrc", "tf_kernels.hip"), os.path.join(PKG, "csrc", "tf_iface.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("tf_kernels.hip", "tf_iface.hip", "tf_arith.hip")]
 ARCH = os.environ.get("TF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

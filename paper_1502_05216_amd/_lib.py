@@ -22,6 +22,8 @@ ONEX = ("exp1x", "expm1_1x", "log1x", "log1p_1x")
 # the other entry points of the paper's interface
 DOTTED = ("pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0")
 COUPLED = ("texpp", "pexp", "texpm1p", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p")
+# twofold arithmetic: binary operations, and the square root
+ARITH = ("tadd", "tsub", "tmul", "tdiv")
 
 _lib = None
 
@@ -51,6 +53,15 @@ def _load():
             fn = getattr(lib, "tf_" + f + sfx)
             fn.argtypes = [P, P, P, S, P]
             fn.restype = ctypes.c_int
+    for f in ARITH:
+        for sfx in ("", "f"):
+            fn = getattr(lib, "tf_" + f + sfx)
+            fn.argtypes = [P, P, P, P, P, P, S, P]
+            fn.restype = ctypes.c_int
+    for sfx in ("", "f"):
+        fn = getattr(lib, "tf_tsqrt" + sfx)
+        fn.argtypes = [P, P, P, P, S, P]
+        fn.restype = ctypes.c_int
     for f in ONEX:
         for sfx in ("", "f"):
             fn = getattr(lib, "tf_" + f + sfx)
@@ -116,9 +127,9 @@ def _validate(*ts):
 
 
 def twofold_call(name, x0, x1, out=None):
-    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD or COUPLED."""
+    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD or COUPLED, or tsqrt."""
     import torch
-    if name not in TWOFOLD + COUPLED:
+    if name not in TWOFOLD + COUPLED + ("tsqrt",):
         raise ValueError(name)
     _validate(x0, x1)
     if out is None:
@@ -150,6 +161,25 @@ def dotted_call(name, x0, out=None):
     with torch.cuda.device(x0.device):
         _check(fn(x0.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(), _stream()),
                "tf_" + name)
+    return z0, z1
+
+
+def arith_call(name, x0, x1, y0, y1, out=None):
+    """z0, z1 = (x0 + x1) op (y0 + y1) elementwise; name in ARITH."""
+    import torch
+    if name not in ARITH:
+        raise ValueError(name)
+    _validate(x0, x1, y0, y1)
+    if out is None:
+        z0 = torch.empty_like(x0)
+        z1 = torch.empty_like(x0)
+    else:
+        z0, z1 = out
+        _validate(x0, z0, z1)
+    fn = getattr(_load(), "tf_" + name + _suffix(x0))
+    with torch.cuda.device(x0.device):
+        _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), z0.data_ptr(),
+                  z1.data_ptr(), x0.numel(), _stream()), "tf_" + name)
     return z0, z1
 
 

@@ -158,6 +158,17 @@ template <class T> __device__ __forceinline__ Tw<T> div_tt(Tw<T> A, Tw<T> B) {
     T q1 = ((r + A.x1) - q0 * B.x1) / B.x0;
     return {q0, q1};
 }
+// d + t = a - b exactly, any a, b (the corrected subtraction algorithm).
+template <class T> __device__ __forceinline__ Tw<T> two_diff(T a, T b) {
+    T d = a - b;
+    T bp = d - a;
+    T ap = d - bp;
+    T bs = b + bp;
+    T as = a - ap;
+    return {d, as - bs};
+}
+__device__ __forceinline__ double fsqrt(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ float fsqrt(float a) { return __builtin_sqrtf(a); }
 template <class T> __device__ __forceinline__ Tw<T> sel(bool c, Tw<T> a, Tw<T> b) {
     return {c ? a.x0 : b.x0, c ? a.x1 : b.x1};
 }

@@ -21,7 +21,8 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--fn", default="all",
                     help="comma-separated names; 'all' = the four twofold functions, "
-                         "'iface' = the other 16 interface functions, 'everything' = both")
+                         "'iface' = the other 16 interface functions, 'arith' = the twofold "
+                         "arithmetic, 'everything' = all of them")
     args = ap.parse_args()
 
     import torch
@@ -39,26 +40,40 @@ def main():
         funcs = tf.TWOFOLD
     elif args.fn == "iface":
         funcs = tf.DOTTED + tf.COUPLED
+    elif args.fn == "arith":
+        funcs = tf.ARITH + ("tsqrt",)
     elif args.fn == "everything":
-        funcs = tf.TWOFOLD + tf.DOTTED + tf.COUPLED
+        funcs = tf.TWOFOLD + tf.DOTTED + tf.COUPLED + tf.ARITH + ("tsqrt",)
     else:
         funcs = tuple(args.fn.split(","))
     for dname in args.dtype.split(","):
         dt = {"f64": np.float64, "f32": np.float32}[dname]
         for fn in funcs:
-            a, b = workloads.twofold_inputs(fn, args.n, dt, coupled=fn in tf.COUPLED)
+            arith = fn in tf.ARITH or fn == "tsqrt"
+            # the arithmetic takes texp's argument law (twofolds of many magnitudes)
+            a, b = workloads.twofold_inputs("texp" if arith else fn, args.n, dt,
+                                            coupled=fn in tf.COUPLED)
             x0 = torch.from_numpy(a).to(dev)
             x1 = torch.from_numpy(b).to(dev)
             z0 = torch.empty_like(x0)
             z1 = torch.empty_like(x0)
+            if arith:                          # y = the same twofolds reversed
+                y0, y1 = x0.flip(0), x1.flip(0)
+                ax0 = x0.abs()
             for _ in range(args.reps):
                 if fn in tf.DOTTED:
                     getattr(tf, fn)(x0, out=(z0, z1))
+                elif fn in tf.ARITH:
+                    getattr(tf, fn)(x0, x1, y0, y1, out=(z0, z1))
+                elif fn == "tsqrt":
+                    tf.tsqrt(ax0, x1, out=(z0, z1))
                 else:
                     getattr(tf, fn)(x0, x1, out=(z0, z1))
             torch.cuda.synchronize()
             print("%s %s x%d done" % (fn, dname, args.reps), flush=True)
             del x0, x1, z0, z1
+            if arith:
+                del y0, y1, ax0
     return 0
 
 

@@ -27,6 +27,7 @@ from collections import defaultdict
 from ._build import source_hash
 
 FN_NAMES = {0: "texp", 1: "texpm1", 2: "tlog", 3: "tlog1p"}
+ARITH_NAMES = ["tadd", "tsub", "tmul", "tdiv", "tsqrt"]
 IFACE_NAMES = ["pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0",
                "pexp", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p"]
 
@@ -40,6 +41,9 @@ def short_name(kernel):
     m = re.search(r"k_iface<(double|float), (\d+), (\d+)>", kernel)
     if m:
         return "k_iface<%s,%s> ept%s" % (m.group(1), IFACE_NAMES[int(m.group(2))], m.group(3))
+    m = re.search(r"k_arith<(double|float), (\d), (\d+)>", kernel)
+    if m:
+        return "k_arith<%s,%s> ept%s" % (m.group(1), ARITH_NAMES[int(m.group(2))], m.group(3))
     m = re.search(r"k_backward<(double|float), (\d), (\d+)>", kernel)
     if m:
         return "k_backward<%s,%s> ept%s" % (m.group(1), FN_NAMES[int(m.group(2))], m.group(3))
@@ -59,7 +63,19 @@ def traffic_key(kernel):
     m = re.search(r"k_iface<(double|float), (\d+),", kernel)
     if m:
         return ("f64_" if m.group(1) == "double" else "f32_") + IFACE_NAMES[int(m.group(2))]
+    m = re.search(r"k_arith<(double|float), (\d),", kernel)
+    if m:
+        return ("f64_" if m.group(1) == "double" else "f32_") + ARITH_NAMES[int(m.group(2))]
     return None
+
+
+def arrays_per_elem(name):
+    """Arrays a kernel streams per element (inputs + outputs)."""
+    if name in IFACE_NAMES[:8] or name == "tsqrt":
+        return 3 if name != "tsqrt" else 4
+    if name in ARITH_NAMES:
+        return 6
+    return 4
 
 
 def stats(args):
@@ -154,8 +170,7 @@ def traffic(args):
         fk = sum(fetch[k]) / len(fetch[k])
         wk = sum(write[k]) / len(write[k])
         b = fk * 1024 * f_scale + wk * 1024 * w_scale
-        nb = 3 if key.split("_", 1)[1] in IFACE_NAMES[:8] else 4
-        alg = args.n * nb * (8 if key.startswith("f64") else 4)
+        alg = args.n * arrays_per_elem(key.split("_", 1)[1]) * (8 if key.startswith("f64") else 4)
         out["kernels"][key] = {"src_hash": h, "n": args.n, "bytes_per_launch": b,
                                "algorithmic_bytes": alg, "fetch_kib": fk, "write_kib": wk,
                                "dispatches": len(fetch[k])}

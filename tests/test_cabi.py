@@ -152,3 +152,26 @@ def test_coupled_argument_validation(lib, name):
         args = [fake] * 4
         args[k] = None
         assert fn(*args, 10, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tf_" + n + s for n in ("tadd", "tsub", "tmul", "tdiv")
+                                  for s in ("", "f")])
+def test_arith_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, None, None, None, None, 0, None) == 0
+    fake = ctypes.c_void_p(0x1000)
+    for k in range(6):
+        args = [fake] * 6
+        args[k] = None
+        assert fn(*args, 10, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tf_tsqrt", "tf_tsqrtf"])
+def test_tsqrt_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    assert fn(None, None, None, None, 0, None) == 0
+    fake = ctypes.c_void_p(0x1000)
+    for k in range(4):
+        args = [fake] * 4
+        args[k] = None
+        assert fn(*args, 10, None) == 1
