@@ -98,7 +98,7 @@ tf_status launch_arith(const T* x0, const T* x1, const T* y0, const T* y1, T* z0
                     aligned16(z0) && aligned16(z1);
     constexpr int EPT = 16 / sizeof(T);
     const size_t tile = (size_t)kBlock * (al ? EPT : 1);
-    const size_t tiles = n / tile, cap = (size_t)cus * 4;
+    const size_t tiles = n / tile, cap = (size_t)cus * kStreamBpc;
     const unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
     hipStream_t s = (hipStream_t)stream;
     if (al)

@@ -136,6 +136,15 @@ template <class T, int EPT> __device__ __forceinline__ void vstore(T* p, const V
 // ----------------------------------------------------------------------------
 // Host side
 // ----------------------------------------------------------------------------
+// Workgroups per compute unit of the purely streaming kernels (backward,
+// twofold arithmetic).  Measured at 2^26 elements: 2 per CU streams at
+// 5.3-5.4 TB/s, 4 at 4.7-5.2 and 8 or 16 at 3.9-4.8 (more concurrent streams
+// than HBM serves well).
+#ifndef TF_STREAM_BPC
+#define TF_STREAM_BPC 2
+#endif
+constexpr int kStreamBpc = TF_STREAM_BPC;
+
 // Compute units of the current device (cached per device).
 tf_status device_cus(int* cus);
 

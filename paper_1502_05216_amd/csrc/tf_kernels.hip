@@ -6,10 +6,12 @@
 // element on the vector ALUs.  The range-reduction tables of the method are
 // copied once per workgroup into LDS; the kernels are grid-stride loops with a
 // grid of a few workgroups per compute unit, so that copy is amortised over
-// many tiles.  The per-element code is branch-free except for two wave-uniform
-// switches taken with wave votes: the tiny-x1 shortcut of expm1(x1) (the
-// common case of a coupled argument) and the pexp0(x0) - 1 path of texpm1
-// (|x0| > ln 2), which runs only on waves that hold such a lane.
+// many tiles.  A wave whose lanes all hold ordinary arguments runs a
+// straight-line fast body; any other wave runs the general body with the edge
+// handling.  The rare branch of texpm1 (|x0| > ln 2: pexp0(x0) - 1) does not
+// hold the fast body back: such lanes go to a per-wave LDS queue that is
+// drained with full waves.  tlog1p's outer branch (the log of 1 + y) is short
+// and runs under a wave vote inside the fast body.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -165,16 +167,21 @@ template <class T> __device__ __forceinline__ WaveQueue<T> wave_queue(QueueSlots
             reinterpret_cast<T*>(base + C * (sizeof(void*) + sizeof(T))), 0};
 }
 
-// Drains up to 64 deferred texpm1 elements with the general form; their z0
-// was already stored by the fast pass, only z1 is written here.
-template <class T, class L>
-__device__ __forceinline__ void drain_texpm1(const L& lds, WaveQueue<T>& wq, int lane) {
+// Functions whose fast waves defer their rare lanes to the queue: texpm1
+// (|x0| > ln 2: pexp0 - 1).  (Deferring tlog1p's outer branch the same way
+// measured slower than computing it under a wave vote: its branch is short.)
+template <int FN> constexpr bool kDefers = FN == FN_TEXPM1;
+
+// Drains up to 64 deferred elements with the general form; their z0 was
+// already stored by the fast pass, only z1 is written here.
+template <class T, int FN, class L>
+__device__ __forceinline__ void drain_deferred(const L& lds, WaveQueue<T>& wq, int lane) {
     T* dst = nullptr;
     T a = T(1), b = T(0);
     const int taken = wq.pop64(lane, &dst, &a, &b);
     if (lane < taken) {
-        const bool tiny = __all(fabs_(b) < P<T>::EXPM1_TINY);
         T r0, r1;
+        const bool tiny = __all(fabs_(b) < P<T>::EXPM1_TINY);
         texpm1_elem(a, b, tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
         *dst = r1;
     }
@@ -190,7 +197,7 @@ template <class T, int FN, int EPT, int PD, class L>
 __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const T* x0,
                                           const T* x1, T* z0, T* z1, size_t t0, size_t t_end,
                                           size_t step) {
-    constexpr bool QUEUE = FN == FN_TEXPM1;
+    constexpr bool QUEUE = kDefers<FN>;
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t off = (size_t)threadIdx.x * EPT;
     const int lane = threadIdx.x & 63;
@@ -228,7 +235,7 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
                 const bool d = (deferred >> e) & 1u;
                 if (!d) z1[base + e] = r1.v[e];
                 wq.push(d, z1 + base + e, a[0].v[e], b[0].v[e]);
-                if (wq.n >= 64) drain_texpm1<T>(lds, wq, lane);
+                if (wq.n >= 64) drain_deferred<T, FN>(lds, wq, lane);
             }
         } else {
             vstore(z1 + base, r1);
@@ -287,8 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T*
     const size_t nfull = n / TILE;
     WaveQueue<T> wq = wave_queue<T>(qs);
     run_tiles<T, FN, EPT, PD>(lds, wq, x0, x1, z0, z1, blockIdx.x, nfull, gridDim.x);
-    if constexpr (FN == FN_TEXPM1) {
-        while (wq.n > 0) drain_texpm1<T>(lds, wq, threadIdx.x & 63);
+    if constexpr (kDefers<FN>) {
+        while (wq.n > 0) drain_deferred<T, FN>(lds, wq, threadIdx.x & 63);
     }
     if (nfull * TILE < n && blockIdx.x == nfull % gridDim.x)
         run_guarded<T, FN, EPT>(lds, x0, x1, z0, z1, nfull * TILE, n);
@@ -371,14 +378,14 @@ __device__ __forceinline__ void batch_dispatch(BatchLds& lds, WaveQueue<double>&
     }
 }
 
-// Empties the texpm1 queue of the (function, format) being left.
+// Empties the deferred-lane queue of the (function, format) being left.
 __device__ __forceinline__ void batch_drain(BatchLds& lds, WaveQueue<double>& q64,
                                             WaveQueue<float>& q32, int key) {
     const int lane = threadIdx.x & 63;
     if (key == 2) {
-        while (q64.n > 0) drain_texpm1<double>(lds.d_expm1, q64, lane);
+        while (q64.n > 0) drain_deferred<double, FN_TEXPM1>(lds.d_expm1, q64, lane);
     } else if (key == 3) {
-        while (q32.n > 0) drain_texpm1<float>(lds.f_expm1, q32, lane);
+        while (q32.n > 0) drain_deferred<float, FN_TEXPM1>(lds.f_expm1, q32, lane);
     }
 }
 
@@ -589,7 +596,7 @@ tf_status launch_backward(const T* s0, const T* s1, const T* g0, const T* g1, T*
                     aligned16(gx0) && aligned16(gx1);
     constexpr int EPT = 16 / sizeof(T);
     const size_t tile = (size_t)kBlock * (al ? EPT : 1);
-    size_t tiles = n / tile, cap = (size_t)cus * 4;
+    size_t tiles = n / tile, cap = (size_t)cus * kStreamBpc;
     unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
     if (al)
         hipLaunchKernelGGL((k_backward<T, FN, EPT>), dim3(grid), dim3(kBlock), 0,
