@@ -354,8 +354,12 @@ def main():
             x1 = torch.from_numpy(b).to(dev)
             o = (torch.empty_like(x0), torch.empty_like(x0))
             ms = kernel_ms(lambda: getattr(tf, fn)(x0, x1, out=o), (), 10)
+            # packed FP32 is not used, so binary32 issues at the FP64 lane rate:
+            # 39.3 T lane-operations/s (78.6 TFLOP/s counting an FMA as 2)
             per32[fn] = {"ms": ms, "gelem_s": N / ms / 1e6,
                          "fp32_tflops": N * opc["f32"][fn]["flops"] / ms / 1e9,
+                         "issue_frac": N * opc["f32"][fn]["ops"] / (ms * 1e-3)
+                         / (PEAK_FP64_ISSUE_T * 1e12),
                          "hbm_gbs": N * BYTES_PER_ELEM["f32"] / ms / 1e6}
             log("f32 %-7s %.3f ms  %.1f Gelem/s" % (fn, ms, per32[fn]["gelem_s"]))
             del x0, x1, o
