@@ -54,11 +54,11 @@ __global__ __launch_bounds__(kBlock) void k_arith(const T* x0, const T* x1, cons
     for (size_t t = blockIdx.x; t < nfull; t += gridDim.x) {
         const size_t base = t * TILE + off;
         Vec<T, EPT> a, b, c, d, r0, r1;
-        vload(a, x0 + base);
-        vload(b, x1 + base);
+        vload<kStreamNT>(a, x0 + base);
+        vload<kStreamNT>(b, x1 + base);
         if constexpr (!UNARY) {
-            vload(c, y0 + base);
-            vload(d, y1 + base);
+            vload<kStreamNT>(c, y0 + base);
+            vload<kStreamNT>(d, y1 + base);
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(kBlock) void k_arith(const T* x0, const T* x1, cons
             r0.v[e] = r.x0;
             r1.v[e] = r.x1;
         }
-        vstore(z0 + base, r0);
-        vstore(z1 + base, r1);
+        vstore<kStreamNT>(z0 + base, r0);
+        vstore<kStreamNT>(z1 + base, r1);
     }
     const size_t rbase = nfull * TILE;
     if (rbase < n && blockIdx.x == nfull % gridDim.x) {

@@ -95,28 +95,47 @@ template <class T> __device__ __forceinline__ T pad_arg() { return T(0.5); }
 template <class T, int EPT> struct Vec { T v[EPT]; };
 
 // 16-byte vector load/store of a thread's EPT consecutive elements (the
-// pointer is 16-byte aligned: the host checks the base pointers).  Built with
-// -DTF_NONTEMPORAL=1 the streams use non-temporal accesses (no reuse).
-#ifndef TF_NONTEMPORAL
-#define TF_NONTEMPORAL 0
+// pointer is 16-byte aligned: the host checks the base pointers).  NT: the
+// access is non-temporal (streamed data that is not reused).  Measured at
+// 2^26 elements, non-temporal streams are 4-8% faster for the purely
+// streaming kernels (backward, twofold arithmetic, the 1x functions) and 1-9%
+// faster for the twofold-function kernels, except the binary64 exp family
+// (texp, texp0, pexp0, pexp), which is 2% slower with them.  TF_STREAM_NT and
+// TF_COMPUTE_NT (build defines, default 1) switch the two groups.
+#ifndef TF_STREAM_NT
+#define TF_STREAM_NT 1
 #endif
+#ifndef TF_COMPUTE_NT
+#define TF_COMPUTE_NT 1
+#endif
+constexpr bool kStreamNT = TF_STREAM_NT != 0;
+template <class T, bool EXP_FAMILY> constexpr bool compute_nt() {
+    return TF_COMPUTE_NT != 0 && !(sizeof(T) == 8 && EXP_FAMILY);
+}
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <class T, int EPT> __device__ __forceinline__ void vload(Vec<T, EPT>& r, const T* p) {
+template <bool NT, class T, int EPT>
+__device__ __forceinline__ void vload(Vec<T, EPT>& r, const T* p) {
     if constexpr ((sizeof(T) * EPT) % 16 == 0) {
         constexpr int Q = sizeof(T) * EPT / 16, PER = 16 / sizeof(T);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             const u32x4* src = reinterpret_cast<const u32x4*>(p) + k;
-            u32x4 q = TF_NONTEMPORAL ? __builtin_nontemporal_load(src) : *src;
+            u32x4 q;
+            if constexpr (NT) q = __builtin_nontemporal_load(src);
+            else q = *src;
             __builtin_memcpy(&r.v[k * PER], &q, 16);
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) r.v[e] = p[e];
+        for (int e = 0; e < EPT; ++e) {
+            if constexpr (NT) r.v[e] = __builtin_nontemporal_load(p + e);
+            else r.v[e] = p[e];
+        }
     }
 }
-template <class T, int EPT> __device__ __forceinline__ void vstore(T* p, const Vec<T, EPT>& r) {
+template <bool NT, class T, int EPT>
+__device__ __forceinline__ void vstore(T* p, const Vec<T, EPT>& r) {
     if constexpr ((sizeof(T) * EPT) % 16 == 0) {
         constexpr int Q = sizeof(T) * EPT / 16, PER = 16 / sizeof(T);
 #pragma unroll
@@ -124,12 +143,15 @@ template <class T, int EPT> __device__ __forceinline__ void vstore(T* p, const V
             u32x4 q;
             __builtin_memcpy(&q, &r.v[k * PER], 16);
             u32x4* dst = reinterpret_cast<u32x4*>(p) + k;
-            if (TF_NONTEMPORAL) __builtin_nontemporal_store(q, dst);
+            if constexpr (NT) __builtin_nontemporal_store(q, dst);
             else *dst = q;
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) p[e] = r.v[e];
+        for (int e = 0; e < EPT; ++e) {
+            if constexpr (NT) __builtin_nontemporal_store(r.v[e], p + e);
+            else p[e] = r.v[e];
+        }
     }
 }
 

@@ -130,6 +130,7 @@ template <class T, int VF, int EPT>
 __global__ __launch_bounds__(kBlock) void k_iface(const T* x0, const T* x1, T* z0, T* z1,
                                                   size_t n) {
     constexpr bool DOT = VfInfo<VF>::DOTTED;
+    constexpr bool NT = compute_nt<T, VfInfo<VF>::EXP1>();
     __shared__ typename VfLds<T, VF>::type lds;
     lds.load();
     __syncthreads();
@@ -146,18 +147,18 @@ __global__ __launch_bounds__(kBlock) void k_iface(const T* x0, const T* x1, T* z
         }
     size_t t = blockIdx.x;
     if (t < nfull) {
-        vload(a[0], x0 + t * TILE + off);
-        if constexpr (!DOT) vload(b[0], x1 + t * TILE + off);
+        vload<NT>(a[0], x0 + t * TILE + off);
+        if constexpr (!DOT) vload<NT>(b[0], x1 + t * TILE + off);
     }
     for (; t < nfull; t += gridDim.x) {
         const size_t tn = t + gridDim.x;                 // next tile, loaded ahead
         if (tn < nfull) {
-            vload(a[1], x0 + tn * TILE + off);
-            if constexpr (!DOT) vload(b[1], x1 + tn * TILE + off);
+            vload<NT>(a[1], x0 + tn * TILE + off);
+            if constexpr (!DOT) vload<NT>(b[1], x1 + tn * TILE + off);
         }
         iface_tile<T, VF, EPT>(lds, a[0], b[0], r0, r1);
-        vstore(z0 + t * TILE + off, r0);
-        vstore(z1 + t * TILE + off, r1);
+        vstore<NT>(z0 + t * TILE + off, r0);
+        vstore<NT>(z1 + t * TILE + off, r1);
         a[0] = a[1];
         b[0] = b[1];
     }

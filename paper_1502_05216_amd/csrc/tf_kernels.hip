@@ -198,6 +198,7 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
                                           const T* x1, T* z0, T* z1, size_t t0, size_t t_end,
                                           size_t step) {
     constexpr bool QUEUE = kDefers<FN>;
+    constexpr bool NT = compute_nt<T, FN == FN_TEXP>();
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t off = (size_t)threadIdx.x * EPT;
     const int lane = threadIdx.x & 63;
@@ -214,20 +215,20 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
     for (int s = 0; s < PD; ++s) {
         const size_t ts = t0 + (size_t)s * step;
         if (ts < t_end) {
-            vload(a[s], x0 + ts * TILE + off);
-            vload(b[s], x1 + ts * TILE + off);
+            vload<NT>(a[s], x0 + ts * TILE + off);
+            vload<NT>(b[s], x1 + ts * TILE + off);
         }
     }
     for (size_t t = t0; t < t_end; t += step) {
         const size_t tn = t + (size_t)PD * step;
         if (tn < t_end) {
-            vload(a[PD], x0 + tn * TILE + off);
-            vload(b[PD], x1 + tn * TILE + off);
+            vload<NT>(a[PD], x0 + tn * TILE + off);
+            vload<NT>(b[PD], x1 + tn * TILE + off);
         }
         unsigned deferred;
         eval_tile<T, FN, EPT>(lds, a[0], b[0], r0, r1, &deferred);
         const size_t base = t * TILE + off;
-        vstore(z0 + base, r0);
+        vstore<NT>(z0 + base, r0);
         if (QUEUE && __any(deferred != 0)) {
             // z1 of deferred elements is written by the drain, not here
 #pragma unroll
@@ -238,7 +239,7 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
                 if (wq.n >= 64) drain_deferred<T, FN>(lds, wq, lane);
             }
         } else {
-            vstore(z1 + base, r1);
+            vstore<NT>(z1 + base, r1);
         }
 #pragma unroll
         for (int s = 0; s < PD; ++s) {
@@ -441,10 +442,10 @@ __global__ __launch_bounds__(kBlock) void k_onex(const T* x, T* z, size_t n) {
     const size_t off = (size_t)threadIdx.x * EPT;
     for (size_t t = blockIdx.x; t < nfull; t += gridDim.x) {
         Vec<T, EPT> a, r;
-        vload(a, x + t * TILE + off);
+        vload<kStreamNT>(a, x + t * TILE + off);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) r.v[e] = eval1<T, F1>(lds, a.v[e]);
-        vstore(z + t * TILE + off, r);
+        vstore<kStreamNT>(z + t * TILE + off, r);
     }
     const size_t rbase = nfull * TILE;
     if (rbase < n && blockIdx.x == nfull % gridDim.x) {
@@ -469,9 +470,9 @@ __global__ __launch_bounds__(kBlock) void k_onex(const T* x, T* z, size_t n) {
 // grid-stride loop for the ALU-bound logarithms.
 LaunchCfg g_cfg[4][2] = {
     {{4, 6, 2}, {4, 4, 1}},   // texp     {binary64, binary32}
-    {{1, 4, 1}, {1, 6, 2}},   // texpm1
-    {{2, 12, 2}, {4, 16, 2}}, // tlog
-    {{2, 12, 1}, {4, 16, 1}}, // tlog1p
+    {{1, 4, 1}, {2, 12, 1}},  // texpm1
+    {{2, 8, 2}, {4, 16, 2}},  // tlog
+    {{2, 16, 1}, {4, 12, 1}}, // tlog1p
 };
 LaunchCfg g_cfg1[4][2] = {
     {{2, 4, 1}, {4, 4, 1}},   // exp1x
@@ -557,18 +558,18 @@ __global__ __launch_bounds__(kBlock) void k_backward(const T* s0, const T* s1, c
     for (size_t t = blockIdx.x; t < nfull; t += gridDim.x) {
         const size_t base = t * TILE + off;
         Vec<T, EPT> a, b, c, d, r0, r1;
-        vload(a, s0 + base);
-        vload(b, s1 + base);
-        vload(c, g0 + base);
-        vload(d, g1 + base);
+        vload<kStreamNT>(a, s0 + base);
+        vload<kStreamNT>(b, s1 + base);
+        vload<kStreamNT>(c, g0 + base);
+        vload<kStreamNT>(d, g1 + base);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             Tw<T> r = bwd_elem<FN>(Tw<T>{a.v[e], b.v[e]}, Tw<T>{c.v[e], d.v[e]});
             r0.v[e] = r.x0;
             r1.v[e] = r.x1;
         }
-        vstore(gx0 + base, r0);
-        vstore(gx1 + base, r1);
+        vstore<kStreamNT>(gx0 + base, r0);
+        vstore<kStreamNT>(gx1 + base, r1);
     }
     const size_t rbase = nfull * TILE;
     if (rbase < n && blockIdx.x == nfull % gridDim.x) {
