@@ -109,8 +109,11 @@ template <class T, int EPT> struct Vec { T v[EPT]; };
 #define TF_COMPUTE_NT 1
 #endif
 constexpr bool kStreamNT = TF_STREAM_NT != 0;
+#ifndef TF_EXP64_NT
+#define TF_EXP64_NT 0
+#endif
 template <class T, bool EXP_FAMILY> constexpr bool compute_nt() {
-    return TF_COMPUTE_NT != 0 && !(sizeof(T) == 8 && EXP_FAMILY);
+    return TF_COMPUTE_NT != 0 && (TF_EXP64_NT != 0 || !(sizeof(T) == 8 && EXP_FAMILY));
 }
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
