@@ -70,6 +70,8 @@ template <> struct P<double> {
     static constexpr double EXP_XMAX = TFH_D_EXP_XMAX, EXPM1_XMAX = TFH_D_EXPM1_XMAX;
     static constexpr double EXP_XLO = TFH_D_EXP_XLO, EXPM1_XNEG = TFH_D_EXPM1_XNEG;
     static constexpr double EXPM1_TINY = TFH_D_EXPM1_TINY, LOG1P_TINY = TFH_D_LOG1P_TINY;
+    // Highest step of pexpm10's Horner run in twofold arithmetic (horner_fact).
+    static constexpr int EXPM1_TF_J = 6;
     static constexpr int EXP_NC = TFH_D_EXP_NC, LOG_NC = TFH_D_LOG_NC;
     static constexpr double EXP_C[EXP_NC] = {TFH_D_EXP_C_LIST};
     static constexpr double LOG_C[LOG_NC] = {TFH_D_LOG_C_LIST};
@@ -98,6 +100,7 @@ template <> struct P<float> {
     static constexpr float EXP_XMAX = TFH_F_EXP_XMAX, EXPM1_XMAX = TFH_F_EXPM1_XMAX;
     static constexpr float EXP_XLO = TFH_F_EXP_XLO, EXPM1_XNEG = TFH_F_EXPM1_XNEG;
     static constexpr float EXPM1_TINY = TFH_F_EXPM1_TINY, LOG1P_TINY = TFH_F_LOG1P_TINY;
+    static constexpr int EXPM1_TF_J = 3;
     static constexpr int EXP_NC = TFH_F_EXP_NC, LOG_NC = TFH_F_LOG_NC;
     static constexpr float EXP_C[EXP_NC] = {TFH_F_EXP_C_LIST};
     static constexpr float LOG_C[LOG_NC] = {TFH_F_LOG_C_LIST};
@@ -311,10 +314,13 @@ template <bool FAST, class T> __device__ __forceinline__ T log1x(T x, LogTab<T> 
 }
 
 // log1p(x): u + c = 1 + x exactly, log(u) with c folded into r; |x| < 2^-8
-// uses r = x directly.  FAST: -1 < x < inf.
-template <bool FAST, class T> __device__ __forceinline__ T log1p_1x(T x, LogTab<T> t) {
+// uses r = x directly.  FAST: -1 < x < inf.  SMALL: the caller guarantees
+// |x| < 2 (the exponent of x is at most that of 1), so the fast two-sum gives
+// the same exact u + c.
+template <bool FAST, bool SMALL = false, class T>
+__device__ __forceinline__ T log1p_1x(T x, LogTab<T> t) {
     using K = P<T>;
-    Tw<T> u = two_sum(T(1), x);
+    Tw<T> u = SMALL ? fast_two_sum(T(1), x) : two_sum(T(1), x);
     LogSplit<T> ls = log_split(u.x0);
     T invc = t.INVC[ls.i];
     T rhi = ffma(ls.z, invc, T(-1));
@@ -343,12 +349,38 @@ template <bool FAST, class T> __device__ __forceinline__ T log1p_1x(T x, LogTab<
 // ----------------------------------------------------------------------------
 template <class T> struct Scaled { Tw<T> v; int k; };
 
-template <class T> __device__ __forceinline__ Tw<T> horner_exp(T y) {
-    constexpr int N = P<T>::N;
-    Tw<T> p = fast_two_sum(T(N), y);
+// Horner's scheme for sum_{i=J0..N} (N!/i!) y^(i-J0), the integer coefficients
+// of the scaled Taylor sums of pexp0 (J0 = 0) and pexpm10 (J0 = 1); each step
+// j multiplies by y and adds N!/j!, which dominates the product, so the sum is
+// a fast two-sum.  The partial sum of step j enters the result with the
+// weight |y|^(j-J0)/j! relative to its value.  Steps above JT run in 1x
+// arithmetic (one FMA each); JT = N - 1 is the all-twofold scheme.
+//
+// pexpm10 (|y| <= 2^-8) runs steps above EXPM1_TF_J in 1x: their rounding
+// errors weigh at most 2^-113 (binary64) or 2^-52 (binary32) of the result,
+// far below the twofold rounding of the other steps.  pexp0 keeps the
+// all-twofold scheme: the coupled pexp renormalises texp's second part, which
+// can span 2^9 ulps of the main part, so a last-bit change in pexp0's twofold
+// representation would move the renormalised second part by many of its own
+// ulps; with the all-twofold scheme pexp0's result is the paper's, bit for bit.
+template <class T, int N, int J0, int JT> __device__ __forceinline__ Tw<T> horner_fact(T y) {
+    constexpr int TOP = JT >= N - 1 ? N - 2 : JT - 1;   // first twofold step after the start
+    Tw<T> p;
+    if constexpr (JT >= N - 1) {
+        p = fast_two_sum(T(N), y);
+    } else {
+        T q = T(N) + y;
 #pragma unroll
-    for (int j = N - 2; j >= 0; --j) p = add_td_fast(mul_td(p, y), T(fact_ratio(N, j)));
+        for (int j = N - 2; j > JT; --j) q = ffma(q, y, T(fact_ratio(N, j)));
+        p = add_td_fast(two_prod(q, y), T(fact_ratio(N, JT)));
+    }
+#pragma unroll
+    for (int j = TOP; j >= J0; --j) p = add_td_fast(mul_td(p, y), T(fact_ratio(N, j)));
     return p;
+}
+
+template <class T> __device__ __forceinline__ Tw<T> horner_exp(T y) {
+    return horner_fact<T, P<T>::N, 0, P<T>::N - 1>(y);
 }
 
 template <bool FAST, class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab<T> t) {
@@ -389,10 +421,7 @@ template <bool FAST, class T> __device__ __forceinline__ Tw<T> pexpm10_small(T x
     T y = ffma(-nd, T(1.0 / 128), xs);                  // exact
     int n = (int)nd;
     if constexpr (!FAST) n = n < -K::CM1_OFF ? -K::CM1_OFF : (n > K::CM1_OFF ? K::CM1_OFF : n);
-    Tw<T> p = fast_two_sum(T(N1), y);
-#pragma unroll
-    for (int j = N1 - 2; j >= 1; --j) p = add_td_fast(mul_td(p, y), T(fact_ratio(N1, j)));
-    p = mul_td(p, y);
+    Tw<T> p = mul_td(horner_fact<T, N1, 1, K::EXPM1_TF_J>(y), y);
     Tw<T> Tt = mul_tt(p, Tw<T>{K::RCP_HI, K::RCP_LO});
     typename K::V2 c2 = t.CM1[n + K::CM1_OFF];
     Tw<T> C = {c2.x, c2.y};
@@ -504,22 +533,47 @@ __device__ __forceinline__ bool texpm1_small_fast(T x0, T x1, ExpTab<T> et, Pm1T
 // |r0| <= ln 2; in the general form a seed beyond the small range of pexpm10
 // (|r0| > 89/128 or NaN: an argument that is not coupled, or not finite, where
 // a coupled one is due) gives a NaN correction.  FAST: |r0| <= 89/128.
+//
+// On a fast wave the seed is a 1x log of 1 + a (error about an ulp) with a in
+// [-1/2, 1] (up to the coupled second part).  Then m = a s + a = a e^-r0 is
+// close to a/(1 + a) and s = e^-r0 - 1 close to -a/(1 + a): their magnitudes
+// agree to a few ulps, or both are so small that every sum is exact.  So
+// m0 + s0 is exact (Sterbenz), the two-sum of m + s has error 0, and its
+// twofold reduces to the two sums below, bit for bit.
 template <bool FAST, class T>
 __device__ __forceinline__ Tw<T> newton_seeded(Tw<T> a, T r0, Pm1Tab<T> mt) {
     Tw<T> s = pexpm10_small<FAST>(-r0, mt);
-    Tw<T> u = add_tt(add_tt(mul_tt(a, s), a), s);
-    T r1 = u.x0 + u.x1;
-    if constexpr (!FAST) r1 = (fabs_(r0) <= T(0.6953125)) ? r1 : P<T>::qnan();
+    Tw<T> m = add_tt(mul_tt(a, s), a);
+    T r1;
+    if constexpr (FAST) {
+        r1 = (m.x0 + s.x0) + (m.x1 + s.x1);
+    } else {
+        Tw<T> u = add_tt(m, s);
+        r1 = u.x0 + u.x1;
+        r1 = (fabs_(r0) <= T(0.6953125)) ? r1 : P<T>::qnan();
+    }
     return {r0, r1};
 }
 
+// Every caller reduces the argument to |a0 + a1| < 2 (a = z - 1 with z in
+// [1/2, 2], or a = y with y0 in [-1/2, 1]); on a fast wave that is guaranteed,
+// so the seed's 1 + x is a fast two-sum.
 template <bool FAST, class T>
 __device__ __forceinline__ Tw<T> plog_newton(Tw<T> a, LogTab<T> lt, Pm1Tab<T> mt) {
-    return newton_seeded<FAST>(a, log1p_1x<FAST>(a.x0 + a.x1, lt), mt);
+    return newton_seeded<FAST>(a, log1p_1x<FAST, FAST>(a.x0 + a.x1, lt), mt);
 }
 
-template <class T> __device__ __forceinline__ Tw<T> add_n_ln2(Tw<T> X, int n) {
-    return add_tt(X, mul_td(Tw<T>{P<T>::LN2_HI, P<T>::LN2_LO}, (T)n));
+// X + n ln2 (twofold).  FAST: |X0| < 1, as for every caller's Newton result
+// (the log of a reduced argument in [1/2, 2]); then n ln2 = 0 or
+// |n ln2| >= 1/2 has the larger exponent and the sum is a fast two-sum.
+template <bool FAST = false, class T> __device__ __forceinline__ Tw<T> add_n_ln2(Tw<T> X, int n) {
+    Tw<T> L = mul_td(Tw<T>{P<T>::LN2_HI, P<T>::LN2_LO}, (T)n);
+    if constexpr (FAST) {
+        Tw<T> st = fast_two_sum(L.x0, X.x0);
+        return {st.x0, st.x1 + (X.x1 + L.x1)};
+    } else {
+        return add_tt(X, L);
+    }
 }
 
 // w = 2^n z: frexp when w0 < 1/2 or w0 > 2, else n = 0.  Scaling w0 by
@@ -546,7 +600,7 @@ __device__ __forceinline__ void tlog_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt
     int n;
     Tw<T> z = log_scale(v, n);
     Tw<T> a = {z.x0 - T(1), z.x1};                    // exact
-    Tw<T> X = add_n_ln2(plog_newton<FAST>(a, lt, mt), n);
+    Tw<T> X = add_n_ln2<FAST>(plog_newton<FAST>(a, lt, mt), n);
     T x1 = X.x1 + (X.x0 - x0);
     x0o = x0;
     if constexpr (FAST) {
@@ -570,13 +624,21 @@ __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> 
     int nn = 0;
     const bool any_outer = __any(outer);
     if (any_outer) {                                  // log of the renormalised 1 + y
-        w = add_td(v, T(1));
-        w = two_sum(w.x0, w.x1);
+        if constexpr (FAST) {
+            // Outer lanes of a fast wave have v0 > 1 or -1 <= v0 < -1/2 (then
+            // 1 + v0 is exact), with |v1| <= ulp(v0)/2: both sums below are
+            // fast two-sums with the exact errors of the general form.
+            Tw<T> st = fast_two_sum(v.x0, T(1));
+            w = fast_two_sum(st.x0, st.x1 + v.x1);
+        } else {
+            w = add_td(v, T(1));
+            w = two_sum(w.x0, w.x1);
+        }
         Tw<T> z = log_scale(w, nn);
         a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
     }
     Tw<T> X = plog_newton<FAST>(a, lt, mt);
-    if (any_outer) X = sel(outer, add_n_ln2(X, outer ? nn : 0), X);
+    if (any_outer) X = sel(outer, add_n_ln2<FAST>(X, outer ? nn : 0), X);
     T x1 = X.x1 + (X.x0 - x0);
     x0o = x0;
     if constexpr (FAST) {
@@ -715,7 +777,7 @@ __device__ __forceinline__ Tw<T> plog0_core(T y0, LogTab<T> lt, Pm1Tab<T> mt) {
     int n;
     Tw<T> z = log_scale(Tw<T>{y0, T(0)}, n);
     Tw<T> a = {z.x0 - T(1), z.x1};                    // exact
-    return add_n_ln2(newton_seeded<FAST>(a, log1x<FAST>(z.x0, lt), mt), n);
+    return add_n_ln2<FAST>(newton_seeded<FAST>(a, log1x<FAST>(z.x0, lt), mt), n);
 }
 
 // plog core (coupled y, y0 in (0, inf), not renormalised): scale by the
@@ -725,7 +787,7 @@ __device__ __forceinline__ Tw<T> plog_coupled_core(Tw<T> y, LogTab<T> lt, Pm1Tab
     int n;
     Tw<T> z = log_scale(y, n);
     Tw<T> a = {z.x0 - T(1), z.x1};
-    return add_n_ln2(plog_newton<FAST>(a, lt, mt), n);
+    return add_n_ln2<FAST>(plog_newton<FAST>(a, lt, mt), n);
 }
 
 // plog1p0 core (dotted y0 in (-1, inf), not renormalised): outside [-1/2, 1]
@@ -738,9 +800,9 @@ __device__ __forceinline__ Tw<T> plog1p0_core(T y0, LogTab<T> lt, Pm1Tab<T> mt) 
     int n;
     Tw<T> z = log_scale(two_sum(T(1), y0), n);
     Tw<T> a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, Tw<T>{y0, T(0)});
-    T r0 = log1p_1x<FAST>(outer ? a.x0 + a.x1 : y0, lt);
+    T r0 = log1p_1x<FAST, FAST>(outer ? a.x0 + a.x1 : y0, lt);
     Tw<T> X = newton_seeded<FAST>(a, r0, mt);
-    return sel(outer, add_n_ln2(X, outer ? n : 0), X);
+    return sel(outer, add_n_ln2<FAST>(X, outer ? n : 0), X);
 }
 
 // plog1p core (coupled y, y0 in (-1, inf), not renormalised): outside
@@ -758,7 +820,7 @@ __device__ __forceinline__ Tw<T> plog1p_core(Tw<T> y, LogTab<T> lt, Pm1Tab<T> mt
         a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, y);
     }
     Tw<T> X = plog_newton<FAST>(a, lt, mt);
-    if (any_outer) X = sel(outer, add_n_ln2(X, outer ? n : 0), X);
+    if (any_outer) X = sel(outer, add_n_ln2<FAST>(X, outer ? n : 0), X);
     return X;
 }
 
