@@ -258,7 +258,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # After the host-side input generation the GPU has idled for seconds; its
+    # clocks take about 10 steps (20 ms) of this load to settle, so the default
+    # warmup covers that.
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f32", action="store_true", help="skip the binary32 rates")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched launch")

@@ -70,8 +70,9 @@ template <> struct P<double> {
     static constexpr double EXP_XMAX = TFH_D_EXP_XMAX, EXPM1_XMAX = TFH_D_EXPM1_XMAX;
     static constexpr double EXP_XLO = TFH_D_EXP_XLO, EXPM1_XNEG = TFH_D_EXPM1_XNEG;
     static constexpr double EXPM1_TINY = TFH_D_EXPM1_TINY, LOG1P_TINY = TFH_D_LOG1P_TINY;
-    // Highest step of pexpm10's Horner run in twofold arithmetic (horner_fact).
-    static constexpr int EXPM1_TF_J = 6;
+    // Highest Horner step run in twofold arithmetic (horner_fact): pexp0 with
+    // the 1x tail, pexpm10.
+    static constexpr int EXP_TF_J = 7, EXPM1_TF_J = 6;
     static constexpr int EXP_NC = TFH_D_EXP_NC, LOG_NC = TFH_D_LOG_NC;
     static constexpr double EXP_C[EXP_NC] = {TFH_D_EXP_C_LIST};
     static constexpr double LOG_C[LOG_NC] = {TFH_D_LOG_C_LIST};
@@ -100,7 +101,7 @@ template <> struct P<float> {
     static constexpr float EXP_XMAX = TFH_F_EXP_XMAX, EXPM1_XMAX = TFH_F_EXPM1_XMAX;
     static constexpr float EXP_XLO = TFH_F_EXP_XLO, EXPM1_XNEG = TFH_F_EXPM1_XNEG;
     static constexpr float EXPM1_TINY = TFH_F_EXPM1_TINY, LOG1P_TINY = TFH_F_LOG1P_TINY;
-    static constexpr int EXPM1_TF_J = 3;
+    static constexpr int EXP_TF_J = 3, EXPM1_TF_J = 3;
     static constexpr int EXP_NC = TFH_F_EXP_NC, LOG_NC = TFH_F_LOG_NC;
     static constexpr float EXP_C[EXP_NC] = {TFH_F_EXP_C_LIST};
     static constexpr float LOG_C[LOG_NC] = {TFH_F_LOG_C_LIST};
@@ -356,13 +357,15 @@ template <class T> struct Scaled { Tw<T> v; int k; };
 // weight |y|^(j-J0)/j! relative to its value.  Steps above JT run in 1x
 // arithmetic (one FMA each); JT = N - 1 is the all-twofold scheme.
 //
-// pexpm10 (|y| <= 2^-8) runs steps above EXPM1_TF_J in 1x: their rounding
-// errors weigh at most 2^-113 (binary64) or 2^-52 (binary32) of the result,
-// far below the twofold rounding of the other steps.  pexp0 keeps the
-// all-twofold scheme: the coupled pexp renormalises texp's second part, which
-// can span 2^9 ulps of the main part, so a last-bit change in pexp0's twofold
+// pexpm10 (|y| <= 2^-8) runs the steps above EXPM1_TF_J in 1x, pexp0
+// (|y| <= 2^-6) those above EXP_TF_J where its caller allows (TAIL): their
+// rounding errors weigh at most 2^-113 (binary64) or 2^-52 (binary32) of the
+// result, far below the twofold rounding of the other steps.  Callers whose
+// result renormalises a second part spanning many ulps of the main part (the
+// coupled pexp, and the exp-minus-one paths that pexpm1 renormalises) keep
+// pexp0's all-twofold scheme: there a last-bit change in pexp0's twofold
 // representation would move the renormalised second part by many of its own
-// ulps; with the all-twofold scheme pexp0's result is the paper's, bit for bit.
+// ulps, while the all-twofold result is the paper's, bit for bit.
 template <class T, int N, int J0, int JT> __device__ __forceinline__ Tw<T> horner_fact(T y) {
     constexpr int TOP = JT >= N - 1 ? N - 2 : JT - 1;   // first twofold step after the start
     Tw<T> p;
@@ -379,11 +382,13 @@ template <class T, int N, int J0, int JT> __device__ __forceinline__ Tw<T> horne
     return p;
 }
 
-template <class T> __device__ __forceinline__ Tw<T> horner_exp(T y) {
-    return horner_fact<T, P<T>::N, 0, P<T>::N - 1>(y);
+template <bool TAIL, class T> __device__ __forceinline__ Tw<T> horner_exp(T y) {
+    return horner_fact<T, P<T>::N, 0, TAIL ? P<T>::EXP_TF_J : P<T>::N - 1>(y);
 }
 
-template <bool FAST, class T> __device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab<T> t) {
+// TAIL: Horner with the 1x tail (horner_fact).
+template <bool FAST, bool TAIL = false, class T>
+__device__ __forceinline__ Scaled<T> pexp0_core(T x, Pexp0Tab<T> t) {
     using K = P<T>;
     constexpr int SH = K::L + K::K;
     T Md = frint(x * T(1 << K::K));
@@ -397,7 +402,7 @@ template <bool FAST, class T> __device__ __forceinline__ Scaled<T> pexp0_core(T 
         m = m < -K::E_OFF ? -K::E_OFF : (m > K::E_CNT - 1 - K::E_OFF ? K::E_CNT - 1 - K::E_OFF : m);
         n = n < -K::C_OFF ? -K::C_OFF : (n > K::C_OFF ? K::C_OFF : n);
     }
-    Tw<T> Tt = horner_exp(y);
+    Tw<T> Tt = horner_exp<TAIL>(y);
     typename K::V2 e2 = t.E[m + K::E_OFF];
     typename K::V2 c2 = t.C[n + K::C_OFF];
     int k = t.EK[m + K::E_OFF];
@@ -459,14 +464,16 @@ template <class T> __device__ __forceinline__ bool tlog1p_fast_arg(T y0, T y1) {
 }
 
 // texp.  FAST: texp_fast_arg (then z0 is finite and pexp0 is in range).
-template <bool FAST, class T>
+// TAIL: pexp0 with the 1x Horner tail (z1 takes pexp0's value, not its
+// representation, up to its own last bits).
+template <bool FAST, bool TAIL, class T>
 __device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et, Pexp0Tab<T> pt,
                                           T& z0o, T& z1o) {
     using K = P<T>;
     if constexpr (FAST) {
         T z0 = exp1x<true>(x0, et);
         T t1 = expm1_tiny(x1);
-        Scaled<T> s = pexp0_core<true>(x0, pt);
+        Scaled<T> s = pexp0_core<true, TAIL>(x0, pt);
         T z0s = fldexp(z0, -s.k);                     // exact
         T z1s = z0s * t1 + (s.v.x1 + (s.v.x0 - z0s));
         z0o = z0;
@@ -477,7 +484,7 @@ __device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et
         bool in = x0 >= K::EXP_XLO;                   // below: pexp0 gives (0, 0)
         T xc = in ? x0 : K::EXP_XLO;
         xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
-        Scaled<T> s = pexp0_core<false>(xc, pt);
+        Scaled<T> s = pexp0_core<false, TAIL>(xc, pt);
         T v0 = in ? s.v.x0 : T(0);
         T v1 = in ? s.v.x1 : T(0);
         int k = in ? s.k : 0;
@@ -675,13 +682,13 @@ template <bool FAST, class T>
 __device__ __forceinline__ void pexp0_p(T x, Pexp0Tab<T> pt, T& z0o, T& z1o) {
     using K = P<T>;
     if constexpr (FAST) {
-        Scaled<T> s = pexp0_core<true>(x, pt);
+        Scaled<T> s = pexp0_core<true, true>(x, pt);
         Tw<T> r = fast_two_sum(fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k));
         z0o = r.x0;
         z1o = r.x1;
     } else {
         const bool in = x >= K::EXP_XLO && x <= K::EXP_XMAX;
-        Scaled<T> s = pexp0_core<false>(in ? x : T(0), pt);
+        Scaled<T> s = pexp0_core<false, true>(in ? x : T(0), pt);
         Tw<T> r = fast_two_sum(fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k));
         r = sel(x < K::EXP_XLO, Tw<T>{T(0), T(0)}, r);
         r = sel(x > K::EXP_XMAX, Tw<T>{K::INF, K::INF}, r);
@@ -698,7 +705,7 @@ __device__ __forceinline__ void texp0_elem(T x0, ExpTab<T> et, Pexp0Tab<T> pt, T
     using K = P<T>;
     if constexpr (FAST) {
         T z0 = exp1x<true>(x0, et);
-        Scaled<T> s = pexp0_core<true>(x0, pt);
+        Scaled<T> s = pexp0_core<true, true>(x0, pt);
         T z0s = fldexp(z0, -s.k);                     // exact
         z0o = z0;
         z1o = fldexp((s.v.x0 - z0s) + s.v.x1, s.k);
@@ -707,7 +714,7 @@ __device__ __forceinline__ void texp0_elem(T x0, ExpTab<T> et, Pexp0Tab<T> pt, T
         bool in = x0 >= K::EXP_XLO;                   // below: pexp0 gives (0, 0)
         T xc = in ? x0 : K::EXP_XLO;
         xc = (xc <= K::EXP_XMAX) ? xc : K::EXP_XMAX;
-        Scaled<T> s = pexp0_core<false>(xc, pt);
+        Scaled<T> s = pexp0_core<false, true>(xc, pt);
         T v0 = in ? s.v.x0 : T(0);
         T v1 = in ? s.v.x1 : T(0);
         int k = in ? s.k : 0;

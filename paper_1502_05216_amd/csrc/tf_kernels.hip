@@ -64,7 +64,7 @@ template <class T, int FN> __device__ __forceinline__ bool fast_arg(T a, T b) {
 // General form of one element (any argument).
 template <class T, int FN, class L>
 __device__ __forceinline__ void eval_general(const L& lds, T a, T b, bool x1_tiny, T& r0, T& r1) {
-    if constexpr (FN == FN_TEXP) texp_elem<false>(a, b, x1_tiny, lds.et(), lds.pt(), r0, r1);
+    if constexpr (FN == FN_TEXP) texp_elem<false, true>(a, b, x1_tiny, lds.et(), lds.pt(), r0, r1);
     else if constexpr (FN == FN_TEXPM1) texpm1_elem(a, b, x1_tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
     else if constexpr (FN == FN_TLOG) tlog_elem<false>(a, b, lds.lt(), lds.mt(), r0, r1);
     else tlog1p_elem<false>(a, b, lds.lt(), lds.mt(), r0, r1);
@@ -87,7 +87,7 @@ __device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, co
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if constexpr (FN == FN_TEXP) {
-                texp_elem<true>(a.v[e], b.v[e], true, lds.et(), lds.pt(), r0.v[e], r1.v[e]);
+                texp_elem<true, true>(a.v[e], b.v[e], true, lds.et(), lds.pt(), r0.v[e], r1.v[e]);
             } else if constexpr (FN == FN_TEXPM1) {
                 if (texpm1_small_fast(a.v[e], b.v[e], lds.et(), lds.mt(), r0.v[e], r1.v[e]))
                     *deferred |= 1u << e;
