@@ -242,6 +242,28 @@ tf_status tf_tlogf_bwd(const float* s0, const float* s1, const float* g0, const 
 tf_status tf_tlog1pf_bwd(const float* s0, const float* s1, const float* g0, const float* g1, float* gx0,
                          float* gx1, size_t n, void* stream);
 
+/* Backward of a chain y = f[k-1](... f[1](f[0](x))) of k twofold functions
+ * (1 <= k <= TF_CHAIN_MAX), in one pass over the arrays.  fns[j] is stage j's
+ * function (0 texp, 1 texpm1, 2 tlog, 3 tlog1p; stage 0 is applied first in
+ * the forward pass) and (s0[j], s1[j]) its saved forward value, as for
+ * tf_*_bwd.  fns, s0 and s1 are host arrays of k entries (read during the
+ * call); the s0[j], s1[j], g and gx are device arrays of n elements.  With
+ * the upstream gradient g of y, gx is the chain's gradient with respect to
+ * x: the stage adjoints applied from stage k-1 down to stage 0, the same
+ * twofold operations as k calls of tf_*_bwd, so the result equals theirs bit
+ * for bit.  A stage whose saved arrays are those of the next stage (as when
+ * texpm1's output is tlog1p's argument) reads them once.  gx may alias g or a
+ * saved array element for element.  Errors: TF_EINVAL for k outside
+ * [1, TF_CHAIN_MAX], an unknown function id, a NULL host array, or a NULL
+ * device pointer with n > 0 (all checked before any GPU work). */
+#define TF_CHAIN_MAX 8
+tf_status tf_chain_bwd(int k, const int* fns, const double* const* s0, const double* const* s1,
+                       const double* g0, const double* g1, double* gx0, double* gx1, size_t n,
+                       void* stream);
+tf_status tf_chain_bwdf(int k, const int* fns, const float* const* s0, const float* const* s1,
+                        const float* g0, const float* g1, float* gx0, float* gx1, size_t n,
+                        void* stream);
+
 /* --- batched ragged launch --------------------------------------------
  * Many arrays of uneven lengths, each with its own function and format, in
  * one persistent launch captured once into a hipGraph.  The plan copies the

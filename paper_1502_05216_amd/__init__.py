@@ -23,7 +23,8 @@ current stream.  The kernels live in libtwofold_hip.so (csrc/, C ABI in
 include/twofold_hip.h); this package only marshals arguments.
 """
 from ._lib import (ARITH, COUPLED, DOTTED, ONEX, TWOFOLD, TwofoldError, arith_call,
-                   backward_call, declared_functions, dotted_call, lib, onex_call, twofold_call)
+                   backward_call, chain_bwd_call, declared_functions, dotted_call, lib, onex_call,
+                   twofold_call)
 
 
 def texp(x0, x1, out=None):
@@ -74,6 +75,12 @@ def tlog1p_bwd(s0, s1, g0, g1, out=None):
     return backward_call("tlog1p", s0, s1, g0, g1, out)
 
 
+def chain_bwd(names, saved, g0, g1, out=None):
+    """Gradient of the chain y = names[-1](... names[0](x)) from the saved
+    forward values of its stages, in one pass (see chain_bwd_call)."""
+    return chain_bwd_call(names, saved, g0, g1, out)
+
+
 def _dotted(name):
     def f(x0, out=None):
         return dotted_call(name, x0, out)
@@ -117,6 +124,6 @@ def build(verbose=False):
 
 
 __all__ = ["texp", "texpm1", "tlog", "tlog1p", "exp1x", "expm1_1x", "log1x", "log1p_1x",
-           "texp_bwd", "texpm1_bwd", "tlog_bwd", "tlog1p_bwd",
+           "texp_bwd", "texpm1_bwd", "tlog_bwd", "tlog1p_bwd", "chain_bwd",
            "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX",
            "DOTTED", "COUPLED", "ARITH", "tsqrt"] + list(DOTTED) + list(COUPLED) + list(ARITH)

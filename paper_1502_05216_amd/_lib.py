@@ -72,6 +72,11 @@ def _load():
             fn = getattr(lib, "tf_" + f + sfx + "_bwd")
             fn.argtypes = [P, P, P, P, P, P, S, P]
             fn.restype = ctypes.c_int
+    for sfx in ("", "f"):
+        fn = getattr(lib, "tf_chain_bwd" + sfx)
+        fn.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(P),
+                       ctypes.POINTER(P), P, P, P, P, S, P]
+        fn.restype = ctypes.c_int
     lib.tf_set_launch_config.argtypes = [ctypes.c_int] * 5
     lib.tf_set_launch_config.restype = ctypes.c_int
     lib.tf_get_launch_config.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
@@ -214,6 +219,46 @@ def backward_call(name, s0, s1, g0, g1, out=None):
     with torch.cuda.device(s0.device):
         _check(fn(s0.data_ptr(), s1.data_ptr(), g0.data_ptr(), g1.data_ptr(), gx0.data_ptr(),
                   gx1.data_ptr(), s0.numel(), _stream()), "tf_" + name + "_bwd")
+    return gx0, gx1
+
+
+CHAIN_MAX = 8          # TF_CHAIN_MAX
+
+
+def chain_bwd_call(names, saved, g0, g1, out=None):
+    """Twofold gradient (gx0, gx1) of y = names[-1](... names[0](x)) with
+    respect to x, for the upstream gradient (g0, g1) of y, in one pass per
+    CHAIN_MAX stages (tf_chain_bwd).  saved[j] = (s0, s1) is stage j's saved
+    forward value as for backward_call; the result equals the chained
+    backward_call results bit for bit."""
+    import torch
+    names = tuple(names)
+    if not names or len(names) != len(saved):
+        raise ValueError("one saved pair per stage, at least one stage")
+    for nm in names:
+        if nm not in TWOFOLD:
+            raise ValueError(nm)
+    _validate(g0, g1, *[t for pair in saved for t in pair])
+    if out is None:
+        gx0 = torch.empty_like(g0)
+        gx1 = torch.empty_like(g0)
+    else:
+        gx0, gx1 = out
+        _validate(g0, gx0, gx1)
+    fn = getattr(_load(), "tf_chain_bwd" + _suffix(g0))
+    cur = (g0, g1)
+    hi = len(names)
+    with torch.cuda.device(g0.device):
+        while hi > 0:                  # the last CHAIN_MAX stages first
+            lo = max(0, hi - CHAIN_MAX)
+            k = hi - lo
+            fns = (ctypes.c_int * k)(*[TWOFOLD.index(nm) for nm in names[lo:hi]])
+            p0 = (ctypes.c_void_p * k)(*[saved[j][0].data_ptr() for j in range(lo, hi)])
+            p1 = (ctypes.c_void_p * k)(*[saved[j][1].data_ptr() for j in range(lo, hi)])
+            _check(fn(k, fns, p0, p1, cur[0].data_ptr(), cur[1].data_ptr(), gx0.data_ptr(),
+                      gx1.data_ptr(), g0.numel(), _stream()), "tf_chain_bwd")
+            cur = (gx0, gx1)
+            hi = lo
     return gx0, gx1
 
 

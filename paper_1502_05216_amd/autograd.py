@@ -71,8 +71,42 @@ class TLog1p(torch.autograd.Function):
         return _backward("tlog1p", ctx, g0, g1)
 
 
+class TChain(torch.autograd.Function):
+    """y = names[-1](... names[0](x)) as one autograd node: the forward runs
+    the stage kernels in order and keeps each stage's saved value (texp and
+    texpm1 their output, tlog and tlog1p their argument); the backward is one
+    fused pass of the library (tf_chain_bwd), equal bit for bit to chaining
+    the single-stage Functions but reading each saved array once and keeping
+    the intermediate gradients in registers."""
+
+    @staticmethod
+    def forward(ctx, names, x0, x1):
+        z = (x0.contiguous(), x1.contiguous())
+        saved = []
+        for name in names:
+            y = _lib.twofold_call(name, *z)
+            saved.append(y if name in ("texp", "texpm1") else z)
+            z = y
+        ctx.names = tuple(names)
+        ctx.save_for_backward(*[t for pair in saved for t in pair])
+        return z
+
+    @staticmethod
+    def backward(ctx, g0, g1):
+        flat = ctx.saved_tensors
+        saved = [(flat[2 * j], flat[2 * j + 1]) for j in range(len(ctx.names))]
+        g0 = torch.zeros_like(flat[0]) if g0 is None else g0.contiguous()
+        g1 = torch.zeros_like(flat[0]) if g1 is None else g1.contiguous()
+        gx0, gx1 = _lib.chain_bwd_call(ctx.names, saved, g0, g1)
+        return None, gx0, gx1
+
+
+def chain(names, x0, x1):
+    """y = names[-1](... names[0](x0 + x1)), differentiable with the fused
+    chain backward; names from texp, texpm1, tlog, tlog1p."""
+    return TChain.apply(tuple(names), x0, x1)
+
+
 def chain_exp_expm1_log1p(x0, x1):
     """y = tlog1p(texpm1(texp(x))) (= e^x in closed form), differentiable."""
-    a0, a1 = TExp.apply(x0, x1)
-    b0, b1 = TExpm1.apply(a0, a1)
-    return TLog1p.apply(b0, b1)
+    return chain(("texp", "texpm1", "tlog1p"), x0, x1)

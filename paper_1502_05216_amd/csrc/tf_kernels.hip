@@ -608,6 +608,126 @@ tf_status launch_backward(const T* s0, const T* s1, const T* g0, const T* g1, T*
     return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
 }
 
+// Backward of a chain of twofold functions in one pass (tf_chain_bwd).  The
+// stage adjoints of k_backward are applied on registers from the last stage
+// to the first, so the gradient equals that of the chained single-stage
+// calls bit for bit, while every saved array is read once (a stage that
+// saved the same arrays as the next one reuses its registers) and the
+// intermediate gradients never reach HBM.  Up to TF_CHAIN_MAX stages; the
+// stage count and functions are kernel arguments, uniform across the grid.
+constexpr int kChainMax = TF_CHAIN_MAX;
+
+template <class T> struct ChainArgs {
+    int k;
+    int fn[kChainMax];
+    int reuse[kChainMax];            // stage j saved the same arrays as stage j + 1
+    const T* s0[kChainMax];
+    const T* s1[kChainMax];
+};
+
+template <class T, int EPT>
+__device__ __forceinline__ void chain_stage(int fn, const Vec<T, EPT>& sa, const Vec<T, EPT>& sb,
+                                            Vec<T, EPT>& ga, Vec<T, EPT>& gb) {
+#define TF_STAGE(F)                                                                          \
+    _Pragma("unroll") for (int e = 0; e < EPT; ++e) {                                        \
+        Tw<T> r = bwd_elem<F>(Tw<T>{sa.v[e], sb.v[e]}, Tw<T>{ga.v[e], gb.v[e]});            \
+        ga.v[e] = r.x0;                                                                      \
+        gb.v[e] = r.x1;                                                                      \
+    }
+    switch (fn) {                    // wave-uniform: a scalar branch
+        case 0: TF_STAGE(0) break;
+        case 1: TF_STAGE(1) break;
+        case 2: TF_STAGE(2) break;
+        default: TF_STAGE(3) break;
+    }
+#undef TF_STAGE
+}
+
+template <class T, int EPT>
+__global__ __launch_bounds__(kBlock) void k_chain_bwd(ChainArgs<T> a, const T* g0, const T* g1,
+                                                      T* gx0, T* gx1, size_t n) {
+    constexpr size_t TILE = (size_t)kBlock * EPT;
+    const size_t nfull = n / TILE;
+    const size_t off = (size_t)threadIdx.x * EPT;
+    for (size_t t = blockIdx.x; t < nfull; t += gridDim.x) {
+        const size_t base = t * TILE + off;
+        Vec<T, EPT> sa[kChainMax], sb[kChainMax], ga, gb;
+        // every load of the element group is issued before the first stage
+#pragma unroll
+        for (int j = kChainMax - 1; j >= 0; --j) {
+            if (j < a.k) {
+                if (j + 1 < a.k && a.reuse[j]) {
+                    sa[j] = sa[j + 1];
+                    sb[j] = sb[j + 1];
+                } else {
+                    vload<kStreamNT>(sa[j], a.s0[j] + base);
+                    vload<kStreamNT>(sb[j], a.s1[j] + base);
+                }
+            }
+        }
+        vload<kStreamNT>(ga, g0 + base);
+        vload<kStreamNT>(gb, g1 + base);
+#pragma unroll
+        for (int j = kChainMax - 1; j >= 0; --j)
+            if (j < a.k) chain_stage<T, EPT>(a.fn[j], sa[j], sb[j], ga, gb);
+        vstore<kStreamNT>(gx0 + base, ga);
+        vstore<kStreamNT>(gx1 + base, gb);
+    }
+    const size_t rbase = nfull * TILE;
+    if (rbase < n && blockIdx.x == nfull % gridDim.x) {
+        for (int e = 0; e < EPT; ++e) {
+            const size_t i = rbase + off + e;
+            if (i < n) {
+                Vec<T, 1> ra, rb;
+                ra.v[0] = g0[i];
+                rb.v[0] = g1[i];
+                for (int j = a.k - 1; j >= 0; --j) {
+                    Vec<T, 1> qa, qb;
+                    qa.v[0] = a.s0[j][i];
+                    qb.v[0] = a.s1[j][i];
+                    chain_stage<T, 1>(a.fn[j], qa, qb, ra, rb);
+                }
+                gx0[i] = ra.v[0];
+                gx1[i] = rb.v[0];
+            }
+        }
+    }
+}
+
+template <class T>
+tf_status launch_chain_bwd(int k, const int* fns, const T* const* s0, const T* const* s1,
+                           const T* g0, const T* g1, T* gx0, T* gx1, size_t n, void* stream) {
+    if (k < 1 || k > kChainMax || !fns || !s0 || !s1) return TF_EINVAL;
+    ChainArgs<T> a{};
+    a.k = k;
+    bool al = aligned16(g0) && aligned16(g1) && aligned16(gx0) && aligned16(gx1);
+    for (int j = 0; j < k; ++j) {
+        if (fns[j] < 0 || fns[j] > 3) return TF_EINVAL;
+        if (n > 0 && (!s0[j] || !s1[j])) return TF_EINVAL;
+        a.fn[j] = fns[j];
+        a.s0[j] = s0[j];
+        a.s1[j] = s1[j];
+        a.reuse[j] = j + 1 < k && s0[j] == s0[j + 1] && s1[j] == s1[j + 1];
+        al = al && aligned16(s0[j]) && aligned16(s1[j]);
+    }
+    if (n == 0) return TF_OK;
+    if (!g0 || !g1 || !gx0 || !gx1) return TF_EINVAL;
+    int cus = 0;
+    tf_status st = device_cus(&cus);
+    if (st != TF_OK) return st;
+    constexpr int EPT = 16 / sizeof(T);
+    const size_t tile = (size_t)kBlock * (al ? EPT : 1);
+    size_t tiles = n / tile, cap = (size_t)cus * kStreamBpc;
+    unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
+    if (al)
+        hipLaunchKernelGGL((k_chain_bwd<T, EPT>), dim3(grid), dim3(kBlock), 0,
+                           (hipStream_t)stream, a, g0, g1, gx0, gx1, n);
+    else
+        hipLaunchKernelGGL((k_chain_bwd<T, 1>), dim3(grid), dim3(kBlock), 0,
+                           (hipStream_t)stream, a, g0, g1, gx0, gx1, n);
+    return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
+}
+
 // Relative cost per element of each (function, format), used to order the
 // chunks of a batch (measured plain-kernel times on 2^26 elements).
 constexpr double kCost[4][2] = {{1.00, 0.46}, {1.25, 0.64}, {1.28, 0.61}, {1.35, 0.60}};
@@ -709,6 +829,17 @@ TF_BWD_ENTRY(tf_texpf_bwd, float, 0)
 TF_BWD_ENTRY(tf_texpm1f_bwd, float, 1)
 TF_BWD_ENTRY(tf_tlogf_bwd, float, 2)
 TF_BWD_ENTRY(tf_tlog1pf_bwd, float, 3)
+
+tf_status tf_chain_bwd(int k, const int* fns, const double* const* s0, const double* const* s1,
+                       const double* g0, const double* g1, double* gx0, double* gx1, size_t n,
+                       void* stream) {
+    return launch_chain_bwd<double>(k, fns, s0, s1, g0, g1, gx0, gx1, n, stream);
+}
+tf_status tf_chain_bwdf(int k, const int* fns, const float* const* s0, const float* const* s1,
+                        const float* g0, const float* g1, float* gx0, float* gx1, size_t n,
+                        void* stream) {
+    return launch_chain_bwd<float>(k, fns, s0, s1, g0, g1, gx0, gx1, n, stream);
+}
 
 tf_status tf_set_launch_config(int fn, int dtype, int ept, int blocks_per_cu, int prefetch) {
     if (fn < 0 || fn > 7 || dtype < 0 || dtype > 1 || (ept != 1 && ept != 2 && ept != 4) ||

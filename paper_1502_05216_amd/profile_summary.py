@@ -47,6 +47,9 @@ def short_name(kernel):
     m = re.search(r"k_backward<(double|float), (\d), (\d+)>", kernel)
     if m:
         return "k_backward<%s,%s> ept%s" % (m.group(1), FN_NAMES[int(m.group(2))], m.group(3))
+    m = re.search(r"k_chain_bwd<(double|float), (\d+)>", kernel)
+    if m:
+        return "k_chain_bwd<%s> ept%s" % (m.group(1), m.group(2))
     m = re.search(r"(k_batch\w*)<?([\d, ]*)>?", kernel)
     if m:
         return m.group(1) + ("<%s>" % m.group(2) if m.group(2) else "")

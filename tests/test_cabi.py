@@ -175,3 +175,36 @@ def test_tsqrt_argument_validation(lib, name):
         args = [fake] * 4
         args[k] = None
         assert fn(*args, 10, None) == 1
+
+
+@pytest.mark.parametrize("name", ["tf_chain_bwd", "tf_chain_bwdf"])
+def test_chain_bwd_argument_validation(lib, name):
+    fn = getattr(lib, name)
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(k, fns, n, s0=None, s1=None, g=(fake, fake, fake, fake)):
+        m = max(len(fns), 1)
+        f = (ctypes.c_int * m)(*fns)
+        p0 = (ctypes.c_void_p * m)(*([fake] * m if s0 is None else s0))
+        p1 = (ctypes.c_void_p * m)(*([fake] * m if s1 is None else s1))
+        return fn(k, f, p0, p1, *g, n, None)
+
+    # stage count outside [1, TF_CHAIN_MAX] and unknown function ids
+    assert call(0, [0], 10) == 1
+    assert call(9, [0] * 9, 10) == 1
+    assert call(-1, [0], 10) == 1
+    assert call(2, [0, 4], 10) == 1
+    assert call(2, [-1, 1], 10) == 1
+    # NULL host arrays
+    assert fn(1, None, None, None, fake, fake, fake, fake, 10, None) == 1
+    # n == 0 with a valid chain: nothing to do, no HIP call
+    assert call(3, [0, 1, 3], 0, g=(None, None, None, None)) == 0
+    assert call(8, [0, 1, 2, 3] * 2, 0, s0=[None] * 8, s1=[None] * 8,
+                g=(None, None, None, None)) == 0
+    # a NULL device array with n > 0, saved or gradient, before any HIP call
+    assert call(2, [0, 2], 10, s0=[fake, None]) == 1
+    assert call(2, [0, 2], 10, s1=[None, fake]) == 1
+    for k in range(4):
+        g = [fake] * 4
+        g[k] = None
+        assert call(2, [1, 3], 10, g=tuple(g)) == 1
