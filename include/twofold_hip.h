@@ -292,7 +292,7 @@ typedef struct {
     int32_t ept32;          /* binary32 arrays: 2 (with ept64 1) or 4 */
     int32_t chunk_tiles;    /* tiles of 256*ept elements per chunk, 1..4096 */
     int32_t blocks_per_cu;  /* workgroups per compute unit, 0 = all resident */
-} tf_batch_config;          /* NULL in tf_batch_plan_create = {2, 4, 16, 0} */
+} tf_batch_config;          /* NULL in tf_batch_plan_create = {2, 4, 32, 0} */
 
 typedef struct tf_batch_plan tf_batch_plan;
 

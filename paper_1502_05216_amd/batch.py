@@ -28,7 +28,7 @@ class BatchConfig(ctypes.Structure):
                 ("chunk_tiles", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
-DEFAULT_CONFIG = (2, 4, 16, 0)
+DEFAULT_CONFIG = (2, 4, 32, 0)
 
 
 def _bind(lib):

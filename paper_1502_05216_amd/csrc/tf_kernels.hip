@@ -392,8 +392,16 @@ __device__ __forceinline__ void batch_drain(BatchLds& lds, WaveQueue<double>& q6
 
 __global__ void k_batch_reset(unsigned* counter) { *counter = 0u; }
 
+// Waves per SIMD asked of the register allocator for the fused batch kernel,
+// which holds the code of all eight (function, format) pairs.  Measured on the
+// 4096-array batch (elements per thread 2/4, 32-tile chunks): 3 waves per SIMD
+// 152 Gelem/s, 4 waves 148, 5 waves 142 (more waves, more spills).
+#ifndef TF_BATCH_WPE
+#define TF_BATCH_WPE 3
+#endif
+
 template <int EPT64, int EPT32>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const BatchDesc* descs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TF_BATCH_WPE))) void k_batch(const BatchDesc* descs,
                                                   const BatchChunk* chunks, unsigned nchunks,
                                                   unsigned* counter, unsigned chunk_tiles) {
     __shared__ BatchLds lds;
@@ -866,7 +874,7 @@ tf_status tf_batch_plan_create(const tf_batch_desc* descs, size_t count,
                                const tf_batch_config* config, tf_batch_plan** out) {
     if (!out || (count > 0 && !descs)) return TF_EINVAL;
     *out = nullptr;
-    tf_batch_config c = {2, 4, 16, 0};
+    tf_batch_config c = {2, 4, 32, 0};
     if (config) c = *config;
     if (!((c.ept64 == 2 && c.ept32 == 4) || (c.ept64 == 4 && c.ept32 == 4) ||
           (c.ept64 == 1 && c.ept32 == 2)) ||
