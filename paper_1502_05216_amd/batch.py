@@ -8,7 +8,10 @@ include/twofold_hip.h).
 
 Arrays are contiguous GPU tensors (float64 or float32 per item); the plan
 keeps references to them until it is closed.  Results equal the plain calls
-bit for bit.
+bit for bit, under every configuration.
+
+    best, times = autotune(items)           # time every candidate configuration
+    plan = BatchPlan(items, config=best)    # or config="tuned": the tune cache
 """
 import ctypes
 
@@ -29,6 +32,12 @@ class BatchConfig(ctypes.Structure):
 
 
 DEFAULT_CONFIG = (2, 4, 32, 0)
+# (elements per thread binary64, binary32) pairs the library instantiates
+EPT_PAIRS = ((2, 4), (1, 2), (4, 4))
+CHUNK_TILES = (8, 16, 32, 64)
+BLOCKS_PER_CU = (0, 2)
+CANDIDATES = tuple((e64, e32, ct, bpc) for e64, e32 in EPT_PAIRS for ct in CHUNK_TILES
+                   for bpc in BLOCKS_PER_CU)
 
 
 def _bind(lib):
@@ -68,6 +77,9 @@ class BatchPlan:
                                    z0.data_ptr(), z1.data_ptr()))
             self._keep += [x0, x1, z0, z1]
         arr = (BatchDesc * max(1, len(descs)))(*descs)
+        if config == "tuned":
+            from . import tune
+            config = tune.batch_config()
         cfg = BatchConfig(*(config or DEFAULT_CONFIG))
         handle = ctypes.c_void_p()
         _lib._check(self._lib.tf_batch_plan_create(arr, len(descs), ctypes.byref(cfg),
@@ -104,3 +116,30 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(items, candidates=CANDIDATES, reps=5, verbose=False):
+    """Time one plan of `items` per candidate configuration (ept64, ept32,
+    chunk_tiles, blocks_per_cu) with HIP events on the current stream and
+    return (best_config, {config: ms per launch}).  The outputs of `items` are
+    overwritten (with the same values under every configuration)."""
+    import torch
+    items = list(items)
+    times = {}
+    stream = torch.cuda.current_stream()
+    for cfg in candidates:
+        cfg = tuple(cfg)
+        with BatchPlan(items, config=cfg) as plan:
+            plan.launch()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                plan.launch()
+            e1.record(stream)
+            e1.synchronize()
+            times[cfg] = e0.elapsed_time(e1) / reps
+        if verbose:
+            print("batch config %s %.4f ms" % (cfg, times[cfg]), flush=True)
+    best = min(times, key=times.get)
+    return best, times

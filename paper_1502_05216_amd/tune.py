@@ -1,7 +1,9 @@
 """Autotuner of the launch configuration (elements per thread, workgroups per
-compute unit) of every kernel, timed with HIP events on the device.
+compute unit) of every kernel, timed with HIP events on the device, and of
+the batched launch (elements per thread, chunk size, workgroups per compute
+unit) on the 4096-array ragged batch.
 
-    python -m paper_1502_05216_amd.tune [--n 67108864] [--out PATH]
+    python -m paper_1502_05216_amd.tune [--n 67108864] [--out PATH] [--batch]
 
 For each function and format it times every candidate on seeded inputs of the
 benchmark distribution (at a size well beyond the last-level cache, so that
@@ -119,6 +121,33 @@ def apply(path=CACHE):
     return True
 
 
+def tune_batch(verbose=True):
+    """Tune the batched launch on the standard ragged batch (4096 arrays of
+    mixed function and format); return {key|batch: [ept64, ept32, chunk_tiles,
+    blocks_per_cu, ms]}."""
+    import torch
+    from . import batch, workloads
+    dev = torch.device("cuda:0")
+    items = []
+    for fn, dt, x0, x1 in workloads.batch_inputs(workloads.batch_descriptors()):
+        a0 = torch.from_numpy(np.ascontiguousarray(x0)).to(dev)
+        a1 = torch.from_numpy(np.ascontiguousarray(x1)).to(dev)
+        items.append((fn, a0, a1, torch.empty_like(a0), torch.empty_like(a0)))
+    best, times = batch.autotune(items, verbose=verbose)
+    if verbose:
+        print("best batch %s %.4f ms" % (best, times[best]), flush=True)
+    return {device_key() + "|batch": list(best) + [times[best]]}
+
+
+def batch_config(path=CACHE):
+    """The tuned batch configuration for the current device, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(device_key() + "|batch")
+    return tuple(int(v) for v in rec[:4]) if rec else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=1 << 26)
@@ -128,7 +157,13 @@ def main():
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--bpcs", default=",".join(map(str, BPCS)))
     ap.add_argument("--epts", default=",".join(map(str, EPTS)))
+    ap.add_argument("--batch", action="store_true", help="tune the batched launch only")
     args = ap.parse_args()
+    if args.batch:
+        r = tune_batch()
+        save(r, args.out)
+        print(json.dumps(r, indent=1))
+        return 0
     r = tune(n=args.n, reps=args.reps, funcs=[f for f in args.funcs.split(",") if f] or None,
              dtypes=tuple(args.dtypes.split(",")), bpcs=tuple(int(b) for b in args.bpcs.split(",")),
              epts=tuple(int(e) for e in args.epts.split(",")))

@@ -115,3 +115,27 @@ def test_full_batch_4096_arrays(tf):
         it = torch.from_numpy(idx).to(outs[k][0].device)
         compare(outs[k][0][it].cpu().numpy(), outs[k][1][it].cpu().numpy(), o0, o1,
                 "full batch %s" % fn)
+
+
+def test_autotune_picks_a_candidate_with_plain_results(tf):
+    """batch.autotune times every candidate on the caller's arrays and returns
+    the fastest; a plan under it still equals the plain calls bit for bit."""
+    from paper_1502_05216_amd.batch import BatchPlan, autotune
+    rng = np.random.default_rng(5)
+    lens = list(rng.integers(1, 30000, 40))
+    descs = [(workloads.FUNCS[i % 4], np.float64 if i % 3 else np.float32, int(n))
+             for i, n in enumerate(lens)]
+    host, items, outs = _make(descs)
+    plain = _plain(tf, items)
+    cands = [(2, 4, 8, 0), (1, 2, 16, 2), (4, 4, 32, 0)]
+    best, times = autotune(items, candidates=cands, reps=2)
+    assert best in cands and set(times) == set(cands)
+    assert all(t > 0 for t in times.values()) and times[best] == min(times.values())
+    torch.cuda.synchronize()
+    _check_equal(items, outs, plain)
+    for _, _, _, z0, z1 in items:
+        z0.fill_(float("nan"))
+    with BatchPlan(items, config=best) as plan:
+        plan.launch()
+        torch.cuda.synchronize()
+    _check_equal(items, outs, plain)

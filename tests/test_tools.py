@@ -75,3 +75,15 @@ def test_profile_summary_trace_and_traffic(tmp_path):
     k = rec["kernels"]["f64_tlog1p"]
     assert k["bytes_per_launch"] == pytest.approx(32 * n)
     assert k["algorithmic_bytes"] == 32 * n
+
+
+def test_batch_candidates_are_valid_configurations():
+    """Every autotuner candidate is a configuration the library accepts:
+    an instantiated (ept64, ept32) pair, chunk_tiles in 1..4096, blocks per
+    compute unit in 0..64 (tf_batch_plan_create's checks)."""
+    from paper_1502_05216_amd import batch
+    assert batch.DEFAULT_CONFIG in batch.CANDIDATES
+    assert len(set(batch.CANDIDATES)) == len(batch.CANDIDATES) >= 12
+    for e64, e32, ct, bpc in batch.CANDIDATES:
+        assert (e64, e32) in ((2, 4), (4, 4), (1, 2))
+        assert 1 <= ct <= 4096 and 0 <= bpc <= 64
