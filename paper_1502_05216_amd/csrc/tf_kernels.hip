@@ -472,15 +472,16 @@ __global__ __launch_bounds__(kBlock) void k_onex(const T* x, T* z, size_t n) {
 // Launch configuration per (function, format): elements per thread and
 // workgroups per compute unit (0 = as many as fit, from the occupancy API).
 // Defaults measured on MI355X (256 CUs) with paper_1502_05216_amd.tune on
-// 2^26-element arrays (beyond the last-level cache); the landscape is flat,
-// the best few configurations being within a few percent of each other.
-// More workgroups than fit at once (bpc 12-16) shorten the tail of the
-// grid-stride loop for the ALU-bound logarithms.
+// 2^26-element arrays (beyond the last-level cache), then checked inside the
+// four-function binary64 step; the landscape is flat, the best few
+// configurations being within a few percent of each other.  More workgroups
+// than fit at once (bpc 12) shorten the tail of the grid-stride loop for the
+// ALU-bound tlog1p.
 LaunchCfg g_cfg[4][2] = {
-    {{4, 6, 2}, {4, 4, 1}},   // texp     {binary64, binary32}
+    {{1, 4, 2}, {4, 4, 1}},   // texp     {binary64, binary32}
     {{1, 4, 1}, {2, 12, 1}},  // texpm1
-    {{2, 8, 2}, {4, 16, 2}},  // tlog
-    {{2, 16, 1}, {4, 12, 1}}, // tlog1p
+    {{2, 6, 2}, {4, 12, 2}},  // tlog
+    {{2, 12, 1}, {4, 12, 1}}, // tlog1p
 };
 LaunchCfg g_cfg1[4][2] = {
     {{2, 4, 1}, {4, 4, 1}},   // exp1x
