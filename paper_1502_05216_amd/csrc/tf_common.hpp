@@ -99,9 +99,12 @@ template <class T, int EPT> struct Vec { T v[EPT]; };
 // access is non-temporal (streamed data that is not reused).  Measured at
 // 2^26 elements, non-temporal streams are 4-8% faster for the purely
 // streaming kernels (backward, twofold arithmetic, the 1x functions) and 1-9%
-// faster for the twofold-function kernels, except the binary64 exp family
-// (texp, texp0, pexp0, pexp), which is 2% slower with them.  TF_STREAM_NT and
-// TF_COMPUTE_NT (build defines, default 1) switch the two groups.
+// faster for the twofold-function kernels.  For binary64 texp (one element
+// per thread) they save 9% of its time, of which the texpm1 launch after it
+// in the four-function step gives back two thirds.  TF_STREAM_NT,
+// TF_COMPUTE_NT and TF_EXP64_NT (build defines, default 1) switch the
+// streaming kernels, the function kernels and, within those, the binary64
+// exp family.
 #ifndef TF_STREAM_NT
 #define TF_STREAM_NT 1
 #endif
@@ -110,7 +113,7 @@ template <class T, int EPT> struct Vec { T v[EPT]; };
 #endif
 constexpr bool kStreamNT = TF_STREAM_NT != 0;
 #ifndef TF_EXP64_NT
-#define TF_EXP64_NT 0
+#define TF_EXP64_NT 1
 #endif
 template <class T, bool EXP_FAMILY> constexpr bool compute_nt() {
     return TF_COMPUTE_NT != 0 && (TF_EXP64_NT != 0 || !(sizeof(T) == 8 && EXP_FAMILY));
