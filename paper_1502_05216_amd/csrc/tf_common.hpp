@@ -100,8 +100,8 @@ template <class T, int EPT> struct Vec { T v[EPT]; };
 // 2^26 elements, non-temporal streams are 4-8% faster for the purely
 // streaming kernels (backward, twofold arithmetic, the 1x functions) and 1-9%
 // faster for the twofold-function kernels.  For binary64 texp (one element
-// per thread) they save 9% of its time, of which the texpm1 launch after it
-// in the four-function step gives back two thirds.  TF_STREAM_NT,
+// per thread) they save 9% of its time, of which texpm1 in the same
+// four-function step gives back two thirds.  TF_STREAM_NT,
 // TF_COMPUTE_NT and TF_EXP64_NT (build defines, default 1) switch the
 // streaming kernels, the function kernels and, within those, the binary64
 // exp family.
