@@ -142,14 +142,24 @@ def test_rejects_bad_arguments(tf):
 @pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
 def test_full_size_sampled(tf, dt):
     """2^26 elements per function (the benchmark's arrays and launch), checked on
-    a random sample of 100000 indices against the oracle."""
+    a random sample of 100000 indices against the oracle, and on every element
+    for the property that z0 is the 1x function of x0 bit for bit (the 1x
+    kernels are pinned against the oracle's 1x functions above)."""
     n = 1 << 26
     d = torch.device("cuda:0")
     rng = np.random.default_rng(99)
+    onex = {"texp": "exp1x", "texpm1": "expm1_1x", "tlog": "log1x", "tlog1p": "log1p_1x"}
+    it_ = torch.int64 if dt == np.float64 else torch.int32
     for fn in FUNCS:
         print("case full-size", fn, np.dtype(dt).name, n, flush=True)
         x0, x1 = workloads.twofold_inputs(fn, n, dt)
-        g0, g1 = getattr(tf, fn)(torch.from_numpy(x0).to(d), torch.from_numpy(x1).to(d))
+        X0 = torch.from_numpy(x0).to(d)
+        g0, g1 = getattr(tf, fn)(X0, torch.from_numpy(x1).to(d))
+        r0 = getattr(tf, onex[fn])(X0)
+        same = (g0.view(it_) == r0.view(it_)) | (torch.isnan(g0) & torch.isnan(r0))
+        assert bool(same.all()), "%s: z0 differs from %s at %d elements" % (
+            fn, onex[fn], int((~same).sum()))
+        del X0, r0, same
         idx = np.sort(rng.choice(n, 100000, replace=False))
         idx = np.concatenate([idx, [0, n - 1]])
         it = torch.from_numpy(idx).to(d)
