@@ -13,7 +13,7 @@ the batched launch over 4096 ragged arrays of mixed function and format
 against the per-array launches and the mix-weighted plain rate; the forward
 and backward chain tlog1p(texpm1(texp(x))) at 2^24; the other entry points of
 the paper's interface at 2^26; the twofold arithmetic (tadd, tsub, tmul, tdiv,
-tsqrt) at 2^26; and the CPU oracle timed on the host cores.
+tsqrt, trenorm) at 2^26; and the CPU oracle timed on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f32]
                     [--no-batch] [--no-chain] [--no-interface] [--no-arith]
@@ -197,9 +197,9 @@ def bench_interface(tf, workloads, opc, reps, dtypes):
 
 
 def bench_arith(tf, reps, dtypes):
-    """Twofold arithmetic (tadd, tsub, tmul, tdiv, tsqrt) on 2^26 elements:
-    48 B per binary64 element for the binary operations, 32 B for tsqrt; all
-    are bound by HBM."""
+    """Twofold arithmetic (tadd, tsub, tmul, tdiv, tsqrt, trenorm) on 2^26
+    elements: 48 B per binary64 element for the binary operations, 32 B for
+    tsqrt and trenorm (of the pair x0, y0); all are bound by HBM."""
     import torch
     dev = torch.device("cuda:0")
     res = {}
@@ -218,9 +218,12 @@ def bench_arith(tf, reps, dtypes):
         out = (torch.empty_like(x0), torch.empty_like(x0))
         res[key] = {}
         isz = 8 if key == "f64" else 4
-        for op in ("tadd", "tsub", "tmul", "tdiv", "tsqrt"):
+        for op in ("tadd", "tsub", "tmul", "tdiv", "tsqrt", "trenorm"):
             if op == "tsqrt":
                 ms = kernel_ms(lambda: tf.tsqrt(ax0, x1, out=out), (), reps)
+                nbytes = 4 * isz
+            elif op == "trenorm":
+                ms = kernel_ms(lambda: tf.trenorm(x0, y0, out=out), (), reps)
                 nbytes = 4 * isz
             else:
                 ms = kernel_ms(lambda: getattr(tf, op)(x0, x1, y0, y1, out=out), (), reps)

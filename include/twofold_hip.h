@@ -190,8 +190,12 @@ tf_status tf_plog1pf(const float* x0, const float* x1, float* z0, float* z1, siz
  *   tmul   z1 = fma(x0, y1, fma(x1, y0, e)),  e = fma(x0, y0, -z0)
  *   tdiv   r = fma(-z0, y0, x0),  z1 = ((r + x1) - z0 y1) / y0
  *   tsqrt  r = fma(-z0, z0, x0),  z1 = (r + x1) / (2 z0)  (0 when x0 = 0)
- * Then the rule for non-finite main parts.  Arrays as above; tsqrt reads
- * x0, x1 only. */
+ *   trenorm  (z0, z1) = two_sum(x0, x1): the renormalized twofold of exactly
+ *          the same value (section "Twofold logarithm", general case), for
+ *          any x0, x1; where |x0| >= |x1| it is the paper's three-operation
+ *          fast renormalization, bit for bit
+ * Then the rule for non-finite main parts.  Arrays as above; tsqrt and
+ * trenorm read x0, x1 only. */
 tf_status tf_tadd(const double* x0, const double* x1, const double* y0, const double* y1,
                   double* z0, double* z1, size_t n, void* stream);
 tf_status tf_tsub(const double* x0, const double* x1, const double* y0, const double* y1,
@@ -212,6 +216,10 @@ tf_status tf_tdivf(const float* x0, const float* x1, const float* y0, const floa
                    float* z1, size_t n, void* stream);
 tf_status tf_tsqrtf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
                     void* stream);
+tf_status tf_trenorm(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                     void* stream);
+tf_status tf_trenormf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                      void* stream);
 
 /* --- backward (twofold adjoints; not part of the paper) ----------------
  * Gradient of a twofold function with respect to its twofold argument

@@ -12,7 +12,7 @@ into oracle/libtfo.so) with numpy-array functions:
     z0, z1 = oracle.pexp(x0, x1)        # coupled argument: texpp pexp texpm1p
                                         # pexpm1 tlogp plog tlog1pp plog1p (+ f)
     z0, z1 = oracle.tadd(x0, x1, y0, y1)   # twofold arithmetic: tadd tsub tmul
-    z0, z1 = oracle.tsqrt(x0, x1)          # tdiv (+ f), tsqrt (+ f)
+    z0, z1 = oracle.tsqrt(x0, x1)          # tdiv (+ f), tsqrt and trenorm (+ f)
     gx0, gx1 = oracle.texp_bwd(s0, s1, g0, g1)
     counts = oracle.op_count("texp", x0, x1)   # {add, mul, fma, other, n}
 
@@ -96,8 +96,9 @@ def _load(path=None):
             getattr(lib, "tfo_%s%s_n" % (base, sfx)).argtypes = [P, P, P, P, P, P, S, I]
             getattr(lib, "tfo_count_%s%s_n" % (base, sfx)).argtypes = [P, P, P, P, S, P]
     for sfx in ("", "f"):
-        getattr(lib, "tfo_tsqrt%s_n" % sfx).argtypes = [P, P, P, P, S, I]
-        getattr(lib, "tfo_count_tsqrt%s_n" % sfx).argtypes = [P, P, S, P]
+        for u in ("tsqrt", "trenorm"):
+            getattr(lib, "tfo_%s%s_n" % (u, sfx)).argtypes = [P, P, P, P, S, I]
+            getattr(lib, "tfo_count_%s%s_n" % (u, sfx)).argtypes = [P, P, S, P]
     lib.tfo_eft_n.argtypes = [I, P, P, P, P, S]
     _libs[path] = lib
     return lib
@@ -187,8 +188,9 @@ def _bind(ns, path=None):
     for b in FUNCS_ARITH:      # same array shape as the backward: 4 in, 2 out
         ns[b] = _mk_bwd(b, np.float64, path)
         ns[b + "f"] = _mk_bwd(b + "f", np.float32, path)
-    ns["tsqrt"] = _mk_tw("tsqrt", np.float64, path)
-    ns["tsqrtf"] = _mk_tw("tsqrtf", np.float32, path)
+    for u in ("tsqrt", "trenorm"):
+        ns[u] = _mk_tw(u, np.float64, path)
+        ns[u + "f"] = _mk_tw(u + "f", np.float32, path)
 
 
 _bind(globals())

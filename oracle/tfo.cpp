@@ -812,6 +812,16 @@ template <class T> T tsqrt(T x0, T x1, T* z1) {
     *z1 = r.x1;
     return r.x0;
 }
+/* Renormalization of an arbitrary twofold (section "Twofold logarithm": the
+ * renormalized twofold with exactly the same value, as the general tlog takes
+ * it from its argument): z0 = RN(x0 + x1) and z1 the exact remainder, by the
+ * corrected two-sum.  Where |x0| >= |x1| this is the paper's "renormalize
+ * fast" (three operations), bit for bit.  Then the rule. */
+template <class T> T trenorm(T x0, T x1, T* z1) {
+    Tw<T> r = rule_tw(two_sum(x0, x1));
+    *z1 = r.x1;
+    return r.x0;
+}
 
 /* Backward (twofold adjoints, not in the paper): for x = x0 + x1 and the saved
  * forward value s (z for texp/texpm1, y for tlog/tlog1p), given the twofold
@@ -998,6 +1008,8 @@ TFO_ARITH(tmulf, float, tmul)
 TFO_ARITH(tdivf, float, tdiv)
 TFO_TW(tsqrt, double, tsqrt)
 TFO_TW(tsqrtf, float, tsqrt)
+TFO_TW(trenorm, double, trenorm)
+TFO_TW(trenormf, float, trenorm)
 
 /* Error-free transforms, exported for their exactness pins. */
 void tfo_eft_n(int which, const double* a, const double* b, double* s, double* t, size_t n) {

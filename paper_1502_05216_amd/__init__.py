@@ -110,6 +110,12 @@ def tsqrt(x0, x1, out=None):
     return twofold_call("tsqrt", x0, x1, out)
 
 
+def trenorm(x0, x1, out=None):
+    """z0, z1: the renormalized twofold of exactly the value x0 + x1
+    (z0 = RN(x0 + x1), z1 the remainder), elementwise."""
+    return twofold_call("trenorm", x0, x1, out)
+
+
 for _n in ARITH:
     globals()[_n] = _arith(_n)
 for _n in DOTTED:
@@ -126,4 +132,4 @@ def build(verbose=False):
 __all__ = ["texp", "texpm1", "tlog", "tlog1p", "exp1x", "expm1_1x", "log1x", "log1p_1x",
            "texp_bwd", "texpm1_bwd", "tlog_bwd", "tlog1p_bwd", "chain_bwd",
            "TwofoldError", "declared_functions", "lib", "build", "TWOFOLD", "ONEX",
-           "DOTTED", "COUPLED", "ARITH", "tsqrt"] + list(DOTTED) + list(COUPLED) + list(ARITH)
+           "DOTTED", "COUPLED", "ARITH", "tsqrt", "trenorm"] + list(DOTTED) + list(COUPLED) + list(ARITH)

@@ -59,9 +59,10 @@ def _load():
             fn.argtypes = [P, P, P, P, P, P, S, P]
             fn.restype = ctypes.c_int
     for sfx in ("", "f"):
-        fn = getattr(lib, "tf_tsqrt" + sfx)
-        fn.argtypes = [P, P, P, P, S, P]
-        fn.restype = ctypes.c_int
+        for u in ("tsqrt", "trenorm"):
+            fn = getattr(lib, "tf_" + u + sfx)
+            fn.argtypes = [P, P, P, P, S, P]
+            fn.restype = ctypes.c_int
     for f in ONEX:
         for sfx in ("", "f"):
             fn = getattr(lib, "tf_" + f + sfx)
@@ -132,9 +133,10 @@ def _validate(*ts):
 
 
 def twofold_call(name, x0, x1, out=None):
-    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD or COUPLED, or tsqrt."""
+    """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD or COUPLED, or tsqrt
+    or trenorm."""
     import torch
-    if name not in TWOFOLD + COUPLED + ("tsqrt",):
+    if name not in TWOFOLD + COUPLED + ("tsqrt", "trenorm"):
         raise ValueError(name)
     _validate(x0, x1)
     if out is None:

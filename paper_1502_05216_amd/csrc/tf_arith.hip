@@ -1,5 +1,6 @@
 // Twofold arithmetic over arrays for gfx950: z = x op y for twofolds
-// x = x0 + x1, y = y0 + y1 (tadd, tsub, tmul, tdiv) and z = sqrt(x) (tsqrt) --
+// x = x0 + x1, y = y0 + y1 (tadd, tsub, tmul, tdiv), z = sqrt(x) (tsqrt) and
+// the renormalization of x (trenorm) --
 // the paper's second measured workload (section "Twofolds update").  The main
 // part is the 1x operation on the main parts (IEEE +, -, *, / and sqrt,
 // correctly rounded); z1 is the twofold error term: the exact error of the
@@ -7,7 +8,7 @@
 // subtraction, the FMA product) or the FMA remainder of a quotient / square
 // root, plus the first-order terms of the low parts.  Then the rule for a
 // non-finite main part.  Each kernel streams its arrays once: 48 B per
-// binary64 element for the binary operations, 32 B for tsqrt.
+// binary64 element for the binary operations, 32 B for tsqrt and trenorm.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -19,7 +20,7 @@ using namespace tfk;
 
 namespace {
 
-enum Op : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4 };
+enum Op : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4, OP_RENORM = 5 };
 
 template <int OP, class T> __device__ __forceinline__ Tw<T> arith(Tw<T> x, Tw<T> y) {
     Tw<T> z;
@@ -32,6 +33,11 @@ template <int OP, class T> __device__ __forceinline__ Tw<T> arith(Tw<T> x, Tw<T>
         z = mul_tt(x, y);
     } else if constexpr (OP == OP_DIV) {
         z = div_tt(x, y);
+    } else if constexpr (OP == OP_RENORM) {
+        // the renormalized twofold of exactly the same value: RN(x0 + x1) and
+        // the exact remainder, for any x0, x1 (where |x0| >= |x1| the fast
+        // renormalization gives these bits)
+        z = two_sum(x.x0, x.x1);
     } else {
         // z0 = sqrt(x0), r = x0 - z0^2 exactly (FMA), z1 = (r + x1) / (2 z0);
         // at x0 = 0 the correction is 0
@@ -43,11 +49,13 @@ template <int OP, class T> __device__ __forceinline__ Tw<T> arith(Tw<T> x, Tw<T>
     return {z.x0, special_rule(z.x0, z.x1)};
 }
 
-// y0, y1 are not read for tsqrt (they may be null).
+// y0, y1 are not read for tsqrt and trenorm (they may be null).
+template <int OP> constexpr bool kUnary = OP == OP_SQRT || OP == OP_RENORM;
+
 template <class T, int OP, int EPT>
 __global__ __launch_bounds__(kBlock) void k_arith(const T* x0, const T* x1, const T* y0,
                                                   const T* y1, T* z0, T* z1, size_t n) {
-    constexpr bool UNARY = OP == OP_SQRT;
+    constexpr bool UNARY = kUnary<OP>;
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t nfull = n / TILE;
     const size_t off = (size_t)threadIdx.x * EPT;
@@ -88,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_arith(const T* x0, const T* x1, cons
 template <class T, int OP>
 tf_status launch_arith(const T* x0, const T* x1, const T* y0, const T* y1, T* z0, T* z1, size_t n,
                        void* stream) {
-    constexpr bool UNARY = OP == OP_SQRT;
+    constexpr bool UNARY = kUnary<OP>;
     if (n == 0) return TF_OK;
     if (!x0 || !x1 || (!UNARY && (!y0 || !y1)) || !z0 || !z1) return TF_EINVAL;
     int cus = 0;
@@ -136,6 +144,14 @@ tf_status tf_tsqrt(const double* x0, const double* x1, double* z0, double* z1, s
 tf_status tf_tsqrtf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
                     void* stream) {
     return launch_arith<float, OP_SQRT>(x0, x1, nullptr, nullptr, z0, z1, n, stream);
+}
+tf_status tf_trenorm(const double* x0, const double* x1, double* z0, double* z1, size_t n,
+                     void* stream) {
+    return launch_arith<double, OP_RENORM>(x0, x1, nullptr, nullptr, z0, z1, n, stream);
+}
+tf_status tf_trenormf(const float* x0, const float* x1, float* z0, float* z1, size_t n,
+                      void* stream) {
+    return launch_arith<float, OP_RENORM>(x0, x1, nullptr, nullptr, z0, z1, n, stream);
 }
 
 }  // extern "C"

@@ -41,15 +41,15 @@ def main():
     elif args.fn == "iface":
         funcs = tf.DOTTED + tf.COUPLED
     elif args.fn == "arith":
-        funcs = tf.ARITH + ("tsqrt",)
+        funcs = tf.ARITH + ("tsqrt", "trenorm")
     elif args.fn == "everything":
-        funcs = tf.TWOFOLD + tf.DOTTED + tf.COUPLED + tf.ARITH + ("tsqrt",)
+        funcs = tf.TWOFOLD + tf.DOTTED + tf.COUPLED + tf.ARITH + ("tsqrt", "trenorm")
     else:
         funcs = tuple(args.fn.split(","))
     for dname in args.dtype.split(","):
         dt = {"f64": np.float64, "f32": np.float32}[dname]
         for fn in funcs:
-            arith = fn in tf.ARITH or fn == "tsqrt"
+            arith = fn in tf.ARITH or fn in ("tsqrt", "trenorm")
             # the arithmetic takes texp's argument law (twofolds of many magnitudes)
             a, b = workloads.twofold_inputs("texp" if arith else fn, args.n, dt,
                                             coupled=fn in tf.COUPLED)
@@ -67,6 +67,8 @@ def main():
                     getattr(tf, fn)(x0, x1, y0, y1, out=(z0, z1))
                 elif fn == "tsqrt":
                     tf.tsqrt(ax0, x1, out=(z0, z1))
+                elif fn == "trenorm":
+                    tf.trenorm(x0, y0, out=(z0, z1))
                 else:
                     getattr(tf, fn)(x0, x1, out=(z0, z1))
             torch.cuda.synchronize()

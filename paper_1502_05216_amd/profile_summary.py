@@ -27,7 +27,7 @@ from collections import defaultdict
 from ._build import source_hash
 
 FN_NAMES = {0: "texp", 1: "texpm1", 2: "tlog", 3: "tlog1p"}
-ARITH_NAMES = ["tadd", "tsub", "tmul", "tdiv", "tsqrt"]
+ARITH_NAMES = ["tadd", "tsub", "tmul", "tdiv", "tsqrt", "trenorm"]
 IFACE_NAMES = ["pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p0", "tlog1p0",
                "pexp", "pexpm1", "tlogp", "plog", "tlog1pp", "plog1p"]
 
@@ -74,8 +74,8 @@ def traffic_key(kernel):
 
 def arrays_per_elem(name):
     """Arrays a kernel streams per element (inputs + outputs)."""
-    if name in IFACE_NAMES[:8] or name == "tsqrt":
-        return 3 if name != "tsqrt" else 4
+    if name in IFACE_NAMES[:8] or name in ("tsqrt", "trenorm"):
+        return 3 if name in IFACE_NAMES[:8] else 4
     if name in ARITH_NAMES:
         return 6
     return 4

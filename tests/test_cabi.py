@@ -166,8 +166,8 @@ def test_arith_argument_validation(lib, name):
         assert fn(*args, 10, None) == 1
 
 
-@pytest.mark.parametrize("name", ["tf_tsqrt", "tf_tsqrtf"])
-def test_tsqrt_argument_validation(lib, name):
+@pytest.mark.parametrize("name", ["tf_tsqrt", "tf_tsqrtf", "tf_trenorm", "tf_trenormf"])
+def test_unary_arith_argument_validation(lib, name):
     fn = getattr(lib, name)
     assert fn(None, None, None, None, 0, None) == 0
     fake = ctypes.c_void_p(0x1000)

@@ -1,9 +1,11 @@
-"""GPU parity of the twofold arithmetic (tadd, tsub, tmul, tdiv, tsqrt),
-binary64 and binary32, through the C ABI, against the oracle: random
+"""GPU parity of the twofold arithmetic (tadd, tsub, tmul, tdiv, tsqrt,
+trenorm), binary64 and binary32, through the C ABI, against the oracle: random
 twofolds over many magnitudes with cancellations, special values (zeros,
 infinities, NaN, subnormals) mixed in, ragged sizes, misaligned arrays, and a
 2^24-element run on a sample.  z0 bit for bit (the correctly rounded 1x
-operation), z1 within 4 ulp (in practice bit for bit)."""
+operation), z1 within 4 ulp (in practice bit for bit).  trenorm takes two
+independent numbers (x0, y0) as its pair, so either part may be the larger,
+with cancellations among them."""
 import numpy as np
 import pytest
 
@@ -13,7 +15,7 @@ from parity_util import compare
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-OPS = ("tadd", "tsub", "tmul", "tdiv", "tsqrt")
+OPS = ("tadd", "tsub", "tmul", "tdiv", "tsqrt", "trenorm")
 DTS = (np.float64, np.float32)
 
 
@@ -66,6 +68,9 @@ def run(tf, op, dt, arrs, misalign=False):
     if op == "tsqrt":
         g0, g1 = tf.tsqrt(dev(x0), dev(x1))
         o0, o1 = getattr(oracle, "tsqrt" + sfx(dt))(x0, x1, threads=8)
+    elif op == "trenorm":
+        g0, g1 = tf.trenorm(dev(x0), dev(y0))
+        o0, o1 = getattr(oracle, "trenorm" + sfx(dt))(x0, y0, threads=8)
     else:
         g0, g1 = getattr(tf, op)(dev(x0), dev(x1), dev(y0), dev(y1))
         o0, o1 = getattr(oracle, op + sfx(dt))(x0, x1, y0, y1, threads=8)
@@ -111,6 +116,9 @@ def test_full_size_sampled(tf, dt):
         if op == "tsqrt":
             g0, g1 = tf.tsqrt(dev[0].abs(), dev[1])
             o0, o1 = getattr(oracle, "tsqrt" + sfx(dt))(np.abs(sub[0]), sub[1])
+        elif op == "trenorm":
+            g0, g1 = tf.trenorm(dev[0], dev[2])
+            o0, o1 = getattr(oracle, "trenorm" + sfx(dt))(sub[0], sub[2])
         else:
             g0, g1 = getattr(tf, op)(*dev)
             o0, o1 = getattr(oracle, op + sfx(dt))(*sub)

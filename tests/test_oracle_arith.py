@@ -136,3 +136,40 @@ def test_special_values(dt):
     for op in ("tadd", "tsub", "tmul", "tdiv"):
         z0, z1 = bin_op(op, nan, 0.0, 1.0, 0.0)
         assert np.isnan(z0) and np.isnan(z1)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32], ids=["f64", "f32"])
+def test_trenorm_exact_and_fast_form(dt):
+    """trenorm: z0 + z1 = x0 + x1 exactly (rationals), z0 = RN(x0 + x1), |z1| <= ulp(z0)/2,
+    for any pair (second part larger than the first, cancellation, zeros); where
+    |x0| >= |x1| it equals the paper's three-operation fast renormalization bit for bit."""
+    rng = np.random.default_rng(29)
+    n = 4000
+    x0, _ = _tw(rng, n, dt, -40, 40)
+    x1, _ = _tw(rng, n, dt, -40, 40)                  # any magnitude relative to x0
+    x1[:500] = -x0[:500]                                # exact cancellation
+    x1[500:1000] = (-x0[500:1000] * (dt(1) + dt(2.0 ** -20))).astype(dt)
+    x0[1000:1100] = dt(0)
+    x1[1100:1200] = dt(0)
+    sfx = _sfx(dt)
+    z0, z1 = getattr(oracle, "trenorm" + sfx)(x0, x1)
+    for a, b, r0, r1 in zip(x0, x1, z0, z1):
+        assert _val(r0, r1) == _val(a, b)
+    assert (_bits(z0) == _bits((x0 + x1).astype(dt))).all()
+    assert (np.abs(z1) <= np.spacing(np.abs(z0)) / 2).all()
+    big = np.abs(x0) >= np.abs(x1)
+    s = (x0 + x1).astype(dt)
+    t = (x1 - (s - x0)).astype(dt)
+    assert (_bits(z0[big]) == _bits(s[big])).all() and (_bits(z1[big]) == _bits(t[big])).all()
+    assert big.sum() > 1000 and (~big).sum() > 1000
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32], ids=["f64", "f32"])
+def test_trenorm_special_values(dt):
+    inf, nan = np.inf, np.nan
+    f = getattr(oracle, "trenorm" + _sfx(dt))
+    z0, z1 = f(np.array([inf, 1.0, -inf, nan, inf, 0.0], dt), np.array([1.0, inf, 2.0, 0.0, -inf, -0.0], dt))
+    assert z0[0] == inf and z1[0] == 0 and z0[1] == inf and z1[1] == 0
+    assert z0[2] == -inf and z1[2] == 0
+    assert np.isnan(z0[3]) and np.isnan(z1[3]) and np.isnan(z0[4]) and np.isnan(z1[4])
+    assert z0[5] == 0 and z1[5] == 0

@@ -49,6 +49,8 @@ MUTANTS = {
     "two_diff sign": ("T bs = b + bp;", "T bs = b - bp;"),
     "tdiv dropped y1": ("T q1 = ((r + A.x1) - q0 * B.x1) / B.x0;", "T q1 = (r + A.x1) / B.x0;"),
     "tsqrt remainder sign": ("T r = fma(-z0, z0, x.x0);", "T r = fma(z0, z0, -x.x0);"),
+    "trenorm fast sum for any pair": ("Tw<T> r = rule_tw(two_sum(x0, x1));",
+                                      "Tw<T> r = rule_tw(fast_two_sum(x0, x1));"),
     "plog1p outer 1 + y": ("Tw<T> w = add_td(y, T(1));\n        return plog_coupled_core",
                            "Tw<T> w = add_td(y, T(-1));\n        return plog_coupled_core"),
 }
@@ -110,6 +112,11 @@ def battery_arith(o):
     for a, b, r0, r1 in zip(xs, xs1, z0, z1):
         z = v(r0, r1)
         if not np.isfinite(r1) or abs(z * z - v(a, b)) > abs(F(float(a))) * F(2) ** -100:
+            return False
+    # renormalization keeps the value exactly, whichever part is larger
+    z0, z1 = o.trenorm(y1, x0)
+    for a, b, r0, r1 in zip(y1, x0, z0, z1):
+        if v(r0, r1) != v(a, b):
             return False
     return True
 
