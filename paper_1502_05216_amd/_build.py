@@ -1,5 +1,6 @@
 """Builds libtwofold_hip.so (HIP, gfx950) in-tree with hipcc."""
 import hashlib
+import re
 import os
 import shutil
 import subprocess
@@ -67,15 +68,27 @@ def build(verbose=False, extra=()):
     return LIB
 
 
+def _code_only(text):
+    """C/C++ source without comments and with whitespace runs collapsed (string
+    literals in these sources contain no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash():
-    """Hash of the library's sources (csrc/): ties a measurement to the code it
-    measured."""
+    """Hash of the library's code (csrc/: the HIP sources with comments and
+    whitespace removed, and the table generator): ties a measurement to the
+    code it measured, and survives edits of comments."""
     h = hashlib.sha256()
     d = os.path.join(PKG, "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".hpp", ".inc", ".py")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                text = fh.read()
+            if not f.endswith(".py"):
+                text = _code_only(text)
+            h.update(f.encode() + b"\0" + text.encode())
     return h.hexdigest()[:16]
 
 

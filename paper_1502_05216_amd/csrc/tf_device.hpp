@@ -355,7 +355,9 @@ template <class T> struct Scaled { Tw<T> v; int k; };
 // j multiplies by y and adds N!/j!, which dominates the product, so the sum is
 // a fast two-sum.  The partial sum of step j enters the result with the
 // weight |y|^(j-J0)/j! relative to its value.  Steps above JT run in 1x
-// arithmetic (one FMA each); JT = N - 1 is the all-twofold scheme.
+// arithmetic (one FMA each): section "Twofold exponent / Method summary"
+// notes that a few of the highest-degree terms can be computed in 1x
+// precision; JT = N - 1 is the all-twofold scheme of the algorithm listings.
 //
 // pexpm10 (|y| <= 2^-8) runs the steps above EXPM1_TF_J in 1x, pexp0
 // (|y| <= 2^-6) those above EXP_TF_J where its caller allows (TAIL): their
