@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--cpu-core-sample", type=int, default=1 << 21)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the functions are "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the functions are "
               "elementwise; a multi-GPU run would give each GPU a contiguous element range)",
               file=sys.stderr)
         sys.exit(2)

@@ -33,8 +33,8 @@ def test_table_sizes(f, ne, nc, nm, bytes_ec, bytes_m):
     w = 16 if f == "D" else 8
     assert len(tab(f, "E_HI")) == ne == len(tab(f, "E_LO")) == len(tab(f, "E_K"))
     assert len(tab(f, "C_HI")) == nc and len(tab(f, "CM1_HI")) == nm
-    assert (ne + nc) * w == bytes_ec          # "around 10K bytes" / "around 2K bytes"
-    assert nm * w == bytes_m                  # "around 2.8K" / "1.4K bytes"
+    assert (ne + nc) * w == bytes_ec          # about 10 KB (double) / 2 KB (float), as stated
+    assert nm * w == bytes_m                  # about 2.8 KB / 1.4 KB, as stated
     # index ranges: -744 <= 4m <= 708 (double), -102 <= 2m <= 88 (float)
     L = tab(f, "L")
     off = tab(f, "E_OFF")
