@@ -20,6 +20,7 @@ bytes read and n*8 bytes written), run first in the same process.
 import argparse
 import csv
 import json
+import os
 import re
 import sys
 from collections import defaultdict
@@ -183,6 +184,71 @@ def traffic(args):
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
+def _counters(path):
+    """{kernel: {counter: [values]}} and {kernel: [durations in s]} of a
+    rocprofv3 counter-collection CSV (one row per dispatch and counter)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        k = r["Kernel_Name"]
+        vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[k][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    return vals, {k: list(v.values()) for k, v in dur.items()}
+
+
+def valu(args):
+    """VALU instruction counts of the twofold-function kernels: instructions
+    per element, the clock (GRBM_GUI_ACTIVE counts busy cycles of each XCD),
+    the fraction of VALU issue slots used (a wave64 VALU instruction occupies a
+    SIMD16 for 4 cycles: at most one per CU per cycle), and from the second run
+    the executed FP64 instruction mix against the oracle's algorithmic count."""
+    a, da = _counters(args.csv_a)
+    b, _ = _counters(args.csv_b) if args.csv_b else ({}, {})
+    opc = json.load(open(args.opcounts))
+    mean = lambda v: sum(v) / len(v)
+    lines = ["# VALU instruction counters of the twofold-function kernels, 2^26 elements (MI355X)",
+             "", "Counter runs (from the repository root):", "", "    " + args.command_a]
+    if args.csv_b:
+        lines.append("    " + args.command_b)
+    lines += ["", "Source hash of paper_1502_05216_amd/csrc: %s" % source_hash(), "",
+              "VALU/elem = SQ_INSTS_VALU x 64 / n (wave instructions to lane instructions). "
+              "Clock = GRBM_GUI_ACTIVE / (%d XCDs x dispatch duration). Issue slots used = "
+              "SQ_INSTS_VALU / (%d CUs x cycles): a wave64 instruction takes a SIMD16 four "
+              "cycles at the FP64 rate, so a CU issues at most one per cycle; 32-bit "
+              "instructions can issue faster, so the column is an upper bound for the binary64 "
+              "kernels and is left out for binary32. FP64 columns: "
+              "SQ_INSTS_VALU_{ADD,MUL,FMA}_F64 x 64 / n; executed flops count FMA as 2; the "
+              "algorithmic counts are the oracle's (tests/golden/opcounts.json)."
+              % (args.xcds, args.cus), "",
+              "| kernel | dispatches | us | clock (GHz) | VALU/elem | FP64-rate slots used | "
+              "alg. ops/elem | F64 add | F64 mul | F64 fma | executed flops/elem | "
+              "alg. flops/elem |", "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(a):
+        m = re.search(r"k_twofold<(double|float), (\d),", k)
+        if not m or "SQ_INSTS_VALU" not in a[k]:
+            continue
+        dts = "f64" if m.group(1) == "double" else "f32"
+        fn = FN_NAMES[int(m.group(2))]
+        ins = mean(a[k]["SQ_INSTS_VALU"])
+        d = mean(da[k])
+        cyc = mean(a[k]["GRBM_GUI_ACTIVE"]) / args.xcds
+        row = [short_name(k), str(len(da[k])), "%.1f" % (d * 1e6), "%.2f" % (cyc / d / 1e9),
+               "%.1f" % (ins * 64 / args.n),
+               "%.2f" % (ins / (args.cus * cyc)) if dts == "f64" else "",
+               "%.1f" % opc[dts][fn]["ops"]]
+        if k in b and "SQ_INSTS_VALU_FMA_F64" in b[k]:
+            ad, mu, fm = (mean(b[k]["SQ_INSTS_VALU_%s_F64" % t]) * 64 / args.n
+                          for t in ("ADD", "MUL", "FMA"))
+            row += ["%.1f" % ad, "%.1f" % mu, "%.1f" % fm, "%.1f" % (ad + mu + 2 * fm)]
+        else:
+            row += ["", "", "", ""]
+        row.append("%.1f" % opc[dts][fn]["flops"])
+        lines.append("| " + " | ".join(row) + " |")
+    if args.note:
+        lines += ["", args.note]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -212,8 +278,20 @@ def main():
     t.add_argument("--command-write", required=True)
     t.add_argument("--json", required=True)
     t.add_argument("--out", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("csv_a", help="counter CSV with SQ_INSTS_VALU and GRBM_GUI_ACTIVE")
+    v.add_argument("--csv-b", default="", help="counter CSV with SQ_INSTS_VALU_*_F64")
+    v.add_argument("--n", type=int, default=1 << 26)
+    v.add_argument("--xcds", type=int, default=8)
+    v.add_argument("--cus", type=int, default=256)
+    v.add_argument("--opcounts", default=os.path.join(os.path.dirname(os.path.dirname(
+        os.path.abspath(__file__))), "tests", "golden", "opcounts.json"))
+    v.add_argument("--command-a", required=True)
+    v.add_argument("--command-b", default="")
+    v.add_argument("--note", default="")
+    v.add_argument("--out", required=True)
     args = ap.parse_args()
-    {"stats": stats, "trace": trace, "traffic": traffic}[args.cmd](args)
+    {"stats": stats, "trace": trace, "traffic": traffic, "valu": valu}[args.cmd](args)
 
 
 if __name__ == "__main__":
