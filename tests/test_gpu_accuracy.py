@@ -1,0 +1,88 @@
+"""Accuracy of the GPU results themselves against mpmath (240 bits), not
+against the oracle: the paper's accuracy statements (section "Accuracy") on
+the kernels' own outputs.  The kernels run the paper's operation sequence with
+the 1x Horner tails of pexp0 and pexpm10, so this checks that the tails keep
+the paper's bars: average (L1) and maximum (L0) relative error of z0 + z1 on
+random coupled arguments, binary64 2^-98 / 2^-95 (exp family) and 2^-93 (log
+family), binary32 2^-42 / 2^-38 and 2^-36; results whose second part is
+subnormal are held to the L0 bound plus one subnormal ulp.  Also the
+p-functions pexp0 and pexpm10 (renormalized): coupled, and within 2^-104
+(binary32 2^-45).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mpref
+from paper_1502_05216_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+THR = {("D", "exp"): (-98, -95), ("D", "log"): (-98, -93),
+       ("F", "exp"): (-42, -38), ("F", "log"): (-42, -36)}
+SUB = {"D": (2.0 ** -969, 2.0 ** -1074), "F": (2.0 ** -102, 2.0 ** -149)}
+
+
+@pytest.fixture(scope="module")
+def tf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1502_05216_amd as m
+    m.lib()
+    return m
+
+
+def _gpu(tf, fn, x0, x1=None):
+    d = torch.device("cuda:0")
+    a = torch.from_numpy(np.ascontiguousarray(x0)).to(d)
+    if x1 is None:
+        z0, z1 = getattr(tf, fn)(a)
+    else:
+        z0, z1 = getattr(tf, fn)(a, torch.from_numpy(np.ascontiguousarray(x1)).to(d))
+    torch.cuda.synchronize()
+    return z0.cpu().numpy(), z1.cpu().numpy()
+
+
+@pytest.mark.parametrize("f", ["D", "F"])
+@pytest.mark.parametrize("fn", ["texp", "texpm1", "tlog", "tlog1p"])
+def test_gpu_accuracy_L1_L0(tf, fn, f):
+    dt = np.float64 if f == "D" else np.float32
+    print("case accuracy", fn, f, flush=True)
+    # a 2^16-element launch (many tiles, the production kernels), 2500 sampled
+    n = 1 << 16
+    x0, x1 = workloads.twofold_inputs(fn, n, dt, seed=71 + len(fn), edges=0.0)
+    z0, z1 = _gpu(tf, fn, x0, x1)
+    idx = np.random.default_rng(5).choice(n, 2500, replace=False)
+    fam = "exp" if fn.startswith("texp") else "log"
+    l1, l0 = THR[(f, fam)]
+    rel, sub_bad = [], 0
+    for i in idx:
+        v = mpref.exact(fn, x0[i], x1[i])
+        if v is None or not np.isfinite(z0[i]):
+            continue
+        if abs(v) < SUB[f][0]:
+            if mpref.abs_error(z0[i], z1[i], v) > 2.0 ** l0 * abs(float(v)) + SUB[f][1]:
+                sub_bad += 1
+            continue
+        rel.append(mpref.rel_error(z0[i], z1[i], v))
+    rel = np.array(rel)
+    assert rel.size > 1500
+    print("%s %s: L1 2^%.1f  L0 2^%.1f" % (fn, f, math.log2(rel.mean()), math.log2(rel.max())))
+    assert rel.mean() <= 2.0 ** l1 and rel.max() <= 2.0 ** l0
+    assert sub_bad == 0
+
+
+@pytest.mark.parametrize("f", ["D", "F"])
+def test_gpu_p_functions_coupled_and_accurate(tf, f):
+    dt = np.float64 if f == "D" else np.float32
+    rng = np.random.default_rng(13)
+    bound = -104 if f == "D" else -45
+    x = (rng.uniform(-670, 709, 1500) if f == "D" else rng.uniform(-70, 88, 1500)).astype(dt)
+    for name, fn, xs in (("pexp0", "exp", x), ("pexpm10", "expm1", (x / dt(200)).astype(dt))):
+        v0, v1 = _gpu(tf, name, xs)
+        np.testing.assert_array_equal((v0 + v1).astype(dt), v0)          # coupled
+        worst = max(mpref.rel_error(a, b, mpref.exact(fn, xi)) for xi, a, b in zip(xs, v0, v1))
+        print("%s %s: worst 2^%.1f" % (name, f, math.log2(worst)))
+        assert worst <= 2.0 ** bound, (name, math.log2(worst))
