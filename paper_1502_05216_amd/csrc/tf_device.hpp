@@ -647,7 +647,13 @@ __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> 
         a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
     }
     Tw<T> X = plog_newton<FAST>(a, lt, mt);
-    if (any_outer) X = sel(outer, add_n_ln2<FAST>(X, outer ? nn : 0), X);
+    if constexpr (FAST) {
+        // + 0 ln2 returns X itself up to the sign of a zero second part, which
+        // the final sum below does not keep: no select needed
+        if (any_outer) X = add_n_ln2<FAST>(X, outer ? nn : 0);
+    } else {
+        if (any_outer) X = sel(outer, add_n_ln2<FAST>(X, outer ? nn : 0), X);
+    }
     T x1 = X.x1 + (X.x0 - x0);
     x0o = x0;
     if constexpr (FAST) {
