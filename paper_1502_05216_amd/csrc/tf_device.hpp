@@ -497,6 +497,14 @@ __device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et
     }
 }
 
+// The second part of texpm1 from z0 = expm1(x0), t1 = expm1(x1) and the
+// twofold w = e^x0 - 1: e^(x0 + x1) - 1 - z0 = (z0 + 1) t1 + (w - z0) to
+// first order, w - z0 = w1 + (w0 - z0) with w0 - z0 exact.  Every texpm1 body
+// forms it with this one expression.
+template <class T> __device__ __forceinline__ T texpm1_z1(T z0, T t1, Tw<T> w) {
+    return (z0 + T(1)) * t1 + (w.x1 + (w.x0 - z0));
+}
+
 // texpm1, general form: small path pexpm10, and pexp0(x0) - 1 for |x0| > ln 2
 // on the waves that hold such a lane.
 template <class T>
@@ -515,9 +523,8 @@ __device__ __forceinline__ void texpm1_elem(T x0, T x1, bool x1_tiny, ExpTab<T> 
         w = sel(big, wl, w);
     }
     w = sel(x0 < K::EXP_XLO, Tw<T>{T(-1), T(0)}, w);  // pexp0 = (0, 0) below range
-    T z1 = (z0 + T(1)) * t1 + (w.x1 + (w.x0 - z0));
     z0o = z0;
-    z1o = special_rule(z0, z1);
+    z1o = special_rule(z0, texpm1_z1(z0, t1, w));
 }
 
 // texpm1 on a fast wave (texpm1_fast_arg on every lane), small path only.
@@ -532,8 +539,23 @@ __device__ __forceinline__ bool texpm1_small_fast(T x0, T x1, ExpTab<T> et, Pm1T
     T t1 = expm1_tiny(x1);
     Tw<T> w = pexpm10_small<true>(small ? x0 : T(0), mt);
     z0o = z0;
-    z1o = (z0 + T(1)) * t1 + (w.x1 + (w.x0 - z0));
+    z1o = texpm1_z1(z0, t1, w);
     return !small;
+}
+
+// z1 of a lane that texpm1_small_fast deferred (texpm1_fast_arg holds and
+// |x0| > ln 2), given the z0 it computed: pexp0(x0) - 1 alone.  The fast
+// argument range [EXPM1_XNEG, EXPM1_XMAX] lies inside pexp0's
+// [EXP_XLO, EXP_XMAX] and |x1| < EXPM1_TINY, so this is texpm1_elem's
+// pexp0 branch without its range selects: the same z1, bit for bit.
+template <class T>
+__device__ __forceinline__ T texpm1_big_fast(T x0, T x1, T z0, Pexp0Tab<T> pt) {
+    static_assert(P<T>::EXPM1_XNEG >= P<T>::EXP_XLO && P<T>::EXPM1_XMAX <= P<T>::EXP_XMAX,
+                  "fast texpm1 arguments must lie in pexp0's range");
+    T t1 = expm1_tiny(x1);
+    Scaled<T> s = pexp0_core<true>(x0, pt);
+    Tw<T> w = add_td(Tw<T>{fldexp(s.v.x0, s.k), fldexp(s.v.x1, s.k)}, T(-1));
+    return special_rule(z0, texpm1_z1(z0, t1, w));
 }
 
 // Newton step shared by plog and plog1p: r0 = log1p(a0 + a1), s = pexpm10(-r0),

@@ -106,19 +106,20 @@ __device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, co
 }
 
 // Per-wave queue of deferred elements (texpm1 with |x0| > ln 2): the
-// destination of z1 and the two argument parts, in LDS, appended with a ballot
-// prefix count and drained 64 at a time with one element per lane, so pexp0
-// runs on full waves and the drain reads no global memory.  Entries carry
+// destination of z1, the two argument parts and z0, in LDS, appended with a
+// ballot prefix count and drained 64 at a time with one element per lane, so
+// pexp0 runs on full waves and the drain reads no argument from HBM.  Entries carry
 // their destination pointer, so one queue serves any array.  CAP = 128: the
 // caller drains after every push that brings n to 64 or more.
 template <class T> struct WaveQueue {
     static constexpr int CAP = 128;
-    T** qd;       // this wave's slots: z1 destination, x0, x1
+    T** qd;       // this wave's slots: z1 destination, x0, x1, z0
     T* qa;
     T* qb;
+    T* qz;
     int n;        // entries in use (wave-uniform)
 
-    __device__ void push(bool on, T* dst, T a, T b) {
+    __device__ void push(bool on, T* dst, T a, T b, T z) {
         const unsigned long long m = __ballot(on);
         const int lane_off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -126,6 +127,7 @@ template <class T> struct WaveQueue {
             qd[n + lane_off] = dst;
             qa[n + lane_off] = a;
             qb[n + lane_off] = b;
+            qz[n + lane_off] = z;
         }
         n += __popcll(m);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -133,18 +135,20 @@ template <class T> struct WaveQueue {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // Takes min(n, 64) entries: lane l gets entry l (valid if l < taken).
-    __device__ int pop64(int lane, T** dst, T* a, T* b) {
+    __device__ int pop64(int lane, T** dst, T* a, T* b, T* z) {
         const int taken = n < 64 ? n : 64;
         if (lane < taken) {
             *dst = qd[lane];
             *a = qa[lane];
             *b = qb[lane];
+            *z = qz[lane];
         }
         const int src = 64 + lane;
         if (src < n) {
             qd[lane] = qd[src];
             qa[lane] = qa[src];
             qb[lane] = qb[src];
+            qz[lane] = qz[src];
         }
         n -= taken;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -157,14 +161,15 @@ template <class T> struct WaveQueue {
 // LDS slots of the four per-wave queues of a workgroup (sized for binary64,
 // reused as binary32).
 struct QueueSlots {
-    unsigned char raw[kBlock / 64][WaveQueue<double>::CAP * (sizeof(void*) + 2 * sizeof(double))];
+    unsigned char raw[kBlock / 64][WaveQueue<double>::CAP * (sizeof(void*) + 3 * sizeof(double))];
 };
 
 template <class T> __device__ __forceinline__ WaveQueue<T> wave_queue(QueueSlots& qs) {
     constexpr int C = WaveQueue<T>::CAP;
     unsigned char* base = qs.raw[threadIdx.x / 64];
     return {reinterpret_cast<T**>(base), reinterpret_cast<T*>(base + C * sizeof(void*)),
-            reinterpret_cast<T*>(base + C * (sizeof(void*) + sizeof(T))), 0};
+            reinterpret_cast<T*>(base + C * (sizeof(void*) + sizeof(T))),
+            reinterpret_cast<T*>(base + C * (sizeof(void*) + 2 * sizeof(T))), 0};
 }
 
 // Functions whose fast waves defer their rare lanes to the queue: texpm1
@@ -172,20 +177,30 @@ template <class T> __device__ __forceinline__ WaveQueue<T> wave_queue(QueueSlots
 // measured slower than computing it under a wave vote: its branch is short.)
 template <int FN> constexpr bool kDefers = FN == FN_TEXPM1;
 
-// Drains up to 64 deferred elements with the general form; their z0 was
-// already stored by the fast pass, only z1 is written here.
+// Drains up to 64 deferred elements: pexp0(x0) - 1 alone (texpm1_big_fast),
+// with the z0 the fast pass computed and stored; only z1 is written here.
+// Against the general form (texpm1_elem), this skips a second expm1(x0), the
+// pexpm10 small path and the range selects of every drained element.
 template <class T, int FN, class L>
 __device__ __forceinline__ void drain_deferred(const L& lds, WaveQueue<T>& wq, int lane) {
     T* dst = nullptr;
-    T a = T(1), b = T(0);
-    const int taken = wq.pop64(lane, &dst, &a, &b);
+    T a = T(1), b = T(0), z = T(0);
+    const int taken = wq.pop64(lane, &dst, &a, &b, &z);
     if (lane < taken) {
-        T r0, r1;
-        const bool tiny = __all(fabs_(b) < P<T>::EXPM1_TINY);
-        texpm1_elem(a, b, tiny, lds.et(), lds.pt(), lds.mt(), r0, r1);
-        *dst = r1;
+        // dst points to device memory: a global (not flat) store
+        *(__attribute__((address_space(1))) T*)dst = texpm1_big_fast(a, b, z, lds.pt());
     }
 }
+
+// Whether run_tiles peels its first tile off the loop (the loop then starts in
+// its steady state, see below).  Both forms compute the same values; the
+// choice only changes where the compiler places its memory-counter waits.
+// Measured inside the binary64 step at 2^26 elements per function, peeled:
+// texpm1 and tlog ran about 1% faster, texp 0.5-2% slower, tlog1p the same.
+// Unpeeled, texpm1 with the pexp0-only drain below ran 3% slower than with a
+// drain through the general form: its loop waited on the loads it had just
+// issued.
+template <int FN> constexpr bool kPeel = FN == FN_TEXPM1 || FN == FN_TLOG;
 
 // Full tiles t = t0, t0 + step, ... < t_end of one array (a tile is kBlock*EPT
 // consecutive elements, thread t owning elements t*EPT .. t*EPT+EPT-1, so loads
@@ -219,7 +234,9 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
             vload<NT>(b[s], x1 + ts * TILE + off);
         }
     }
-    for (size_t t = t0; t < t_end; t += step) {
+    // one tile: issue the loads of tile t + PD*step, evaluate and store tile
+    // t, rotate the register sets
+    auto tile_step = [&](size_t t) __attribute__((always_inline)) {
         const size_t tn = t + (size_t)PD * step;
         if (tn < t_end) {
             vload<NT>(a[PD], x0 + tn * TILE + off);
@@ -235,7 +252,7 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
             for (int e = 0; e < EPT; ++e) {
                 const bool d = (deferred >> e) & 1u;
                 if (!d) z1[base + e] = r1.v[e];
-                wq.push(d, z1 + base + e, a[0].v[e], b[0].v[e]);
+                wq.push(d, z1 + base + e, a[0].v[e], b[0].v[e], r0.v[e]);
                 if (wq.n >= 64) drain_deferred<T, FN>(lds, wq, lane);
             }
         } else {
@@ -246,6 +263,17 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
             a[s] = a[s + 1];
             b[s] = b[s + 1];
         }
+    };
+    if constexpr (kPeel<FN>) {
+        // The first tile is peeled off the loop, so the loop is entered in
+        // its steady state (stores of the previous tile in flight after the
+        // loads of the current one) from both sides: the memory-counter waits
+        // the compiler places at the loop head then cover the loads alone,
+        // not the stores.
+        if (t0 < t_end) tile_step(t0);
+        for (size_t t = t0 + step; t < t_end; t += step) tile_step(t);
+    } else {
+        for (size_t t = t0; t < t_end; t += step) tile_step(t);
     }
 }
 
