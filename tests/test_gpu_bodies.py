@@ -1,0 +1,75 @@
+"""GPU: the fast and general bodies of the twofold kernels give the same bits.
+
+A wave whose lanes all hold ordinary arguments runs the straight-line fast body
+(texpm1: the small path, with its |x0| > ln 2 lanes deferred to the wave's
+queue and drained with pexp0 - 1 alone); any other wave runs the general body
+with the edge handling.  For ordinary arguments the two must agree bit for bit.
+The same ordinary inputs run twice: as they are, and with one NaN second part
+in every 64 consecutive elements, which sends every wave (at any number of
+elements per thread) to the general body.  All other elements must come out
+identical.
+"""
+import numpy as np
+import pytest
+
+from paper_1502_05216_amd import workloads
+from parity_util import same_bits
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FUNCS = ("texp", "texpm1", "tlog", "tlog1p")
+DTS = (np.float64, np.float32)
+
+
+@pytest.fixture(scope="module")
+def tf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1502_05216_amd as m
+    from paper_1502_05216_amd import _lib
+    m.lib()
+    saved = {(f, d): _lib.get_launch_config(f, d) for f in FUNCS for d in ("f64", "f32")}
+    yield m
+    for (f, d), c in saved.items():
+        _lib.set_launch_config(f, d, *c)
+
+
+def gpu_call(tf, fn, x0, x1):
+    d = torch.device("cuda:0")
+    g0, g1 = getattr(tf, fn)(torch.from_numpy(x0).to(d), torch.from_numpy(x1).to(d))
+    torch.cuda.synchronize()
+    return g0.cpu().numpy(), g1.cpu().numpy()
+
+
+@pytest.mark.parametrize("ept", [0, 1, 4], ids=["default", "ept1", "ept4"])
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+@pytest.mark.parametrize("fn", FUNCS)
+def test_fast_and_general_bodies_agree(tf, fn, dt, ept):
+    from paper_1502_05216_amd import _lib
+    dts = "f64" if dt == np.float64 else "f32"
+    if ept:
+        _, bpc, pd = _lib.get_launch_config(fn, dts)
+        _lib.set_launch_config(fn, dts, ept, bpc, pd)
+    n = 256 * 4 * 40 + 77
+    x0, x1 = workloads.twofold_inputs(fn, n, dt, seed=91, edges=0.0)
+    print("case", fn, dts, "ept", ept or "default", flush=True)
+    a0, a1 = gpu_call(tf, fn, x0, x1)
+    rng = np.random.default_rng(92)
+    starts = np.arange(0, n, 64)
+    idx = starts + rng.integers(0, 64, size=starts.size)
+    idx = idx[idx < n]
+    p1 = x1.copy()
+    p1[idx] = np.nan
+    b0, b1 = gpu_call(tf, fn, x0, p1)
+    keep = np.ones(n, bool)
+    keep[idx] = False
+    for name, a, b in (("z0", a0, b0), ("z1", a1, b1)):
+        ok = same_bits(a[keep], b[keep])
+        if not ok.all():
+            i = np.flatnonzero(keep)[np.flatnonzero(~ok)[:5]]
+            raise AssertionError("%s %s: %s differs at %d elements, e.g. idx %s x0 %s fast %s "
+                                 "general %s" % (fn, dts, name, (~ok).sum(), i, x0[i], a[i], b[i]))
+    if fn == "texpm1":
+        # the drain really ran: some lanes had |x0| > ln 2
+        assert (np.abs(x0) > 0.7).sum() > 100
