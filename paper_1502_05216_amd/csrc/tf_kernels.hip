@@ -214,6 +214,12 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
                                           size_t step) {
     constexpr bool QUEUE = kDefers<FN>;
     constexpr bool NT = compute_nt<T, FN == FN_TEXP>();
+    // binary32 texpm1 stores z1 through the caches: a line holds 16 elements,
+    // so half of the lines get a drained lane's second write, which can then
+    // merge in the caches.  texpm1 at 2^26 elements: binary32 0.231 ms cached
+    // against 0.260 ms streamed; binary64 0.476 ms streamed against 0.502 ms
+    // cached and 0.502 ms with only the lines that hold a deferred lane cached.
+    constexpr bool NT_Z1 = NT && !(QUEUE && sizeof(T) == 4);
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t off = (size_t)threadIdx.x * EPT;
     const int lane = threadIdx.x & 63;
@@ -253,7 +259,7 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
         // Leaving the deferred lanes out, as masked stores, made 28% of the
         // binary64 z1 lines partial writes (4% of lanes deferred), and texpm1
         // 10% slower at 2^26 elements.
-        vstore<NT>(z1 + base, r1);
+        vstore<NT_Z1>(z1 + base, r1);
         if (QUEUE && __any(deferred != 0)) {
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
