@@ -73,3 +73,26 @@ def test_fast_and_general_bodies_agree(tf, fn, dt, ept):
     if fn == "texpm1":
         # the drain really ran: some lanes had |x0| > ln 2
         assert (np.abs(x0) > 0.7).sum() > 100
+
+
+@pytest.mark.parametrize("frac", [1.0, 0.5], ids=["all", "half"])
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+def test_texpm1_deferred_lanes_against_oracle(tf, dt, frac):
+    """texpm1 where every lane (or every other one) has |x0| > ln 2, so the
+    wave queue fills on every tile and the drain rewrites the z1 of most
+    lines: the result must still meet the parity bar everywhere."""
+    import oracle
+    from parity_util import compare
+    dts = "f64" if dt == np.float64 else "f32"
+    n = 256 * 4 * 33 + 45
+    rng = np.random.default_rng(93)
+    hi = 700.0 if dt == np.float64 else 85.0
+    lo = -40.0 if dt == np.float64 else -20.0
+    big = np.where(rng.random(n) < 0.5, rng.uniform(0.7, hi, n), -rng.uniform(0.7, -lo, n))
+    small = rng.uniform(-0.69, 0.69, n)
+    x0 = np.where(rng.random(n) < frac, big, small).astype(dt)
+    x1 = (x0 * rng.uniform(-1, 1, n).astype(dt) * np.finfo(dt).eps).astype(dt)
+    print("case texpm1", dts, "deferred fraction", frac, flush=True)
+    g0, g1 = gpu_call(tf, "texpm1", x0, x1)
+    o0, o1 = getattr(oracle, "texpm1" + ("" if dt == np.float64 else "f"))(x0, x1)
+    compare(g0, g1, o0, o1, "texpm1 %s deferred %.1f" % (dts, frac))
