@@ -128,6 +128,15 @@ template <class T> __device__ __forceinline__ Tw<T> two_sum(T a, T b) {
     T da = a - ap;
     return {s, da + db};
 }
+// fast_two_sum for |a| >= |b|, with the error formed as (a - s) + b: a - s is
+// exact (the negation of fast_two_sum's exact s - a), so the error has the
+// same value, and an exact sum gives +0 as two_sum's does (b - (s - a) would
+// give -0 for b = -0).  It equals two_sum bit for bit when |a| >= |b|.
+template <class T> __device__ __forceinline__ Tw<T> fast_two_sum_pz(T a, T b) {
+    T s = a + b;
+    T t = (a - s) + b;
+    return {s, t};
+}
 template <class T> __device__ __forceinline__ Tw<T> two_prod(T a, T b) {
     T p = a * b;
     return {p, ffma(a, b, -p)};
@@ -456,13 +465,17 @@ template <class T> __device__ __forceinline__ bool texp_fast_arg(T x0, T x1) {
 template <class T> __device__ __forceinline__ bool texpm1_fast_arg(T x0, T x1) {
     return x0 >= P<T>::EXPM1_XNEG && x0 <= P<T>::EXPM1_XMAX && fabs_(x1) < P<T>::EXPM1_TINY;
 }
+// The log conditions also ask |y1| <= |y0|, so that the first renormalisation
+// two_sum(y0, y1) is fast_two_sum_pz (true of every renormalised or coupled
+// argument).
 template <class T> __device__ __forceinline__ bool tlog_fast_arg(T y0, T y1) {
     T s = y0 + y1;
-    return y0 > T(0) && y0 < P<T>::INF && s > T(0) && s < P<T>::INF;
+    return y0 > T(0) && y0 < P<T>::INF && s > T(0) && s < P<T>::INF && fabs_(y1) <= y0;
 }
 template <class T> __device__ __forceinline__ bool tlog1p_fast_arg(T y0, T y1) {
     T s = y0 + y1;
-    return y0 > T(-1) && y0 < P<T>::INF && s > T(-1) && s < P<T>::INF;
+    return y0 > T(-1) && y0 < P<T>::INF && s > T(-1) && s < P<T>::INF &&
+           fabs_(y1) <= fabs_(y0);
 }
 
 // texp.  FAST: texp_fast_arg (then z0 is finite and pexp0 is in range).
@@ -623,11 +636,11 @@ template <class T> __device__ __forceinline__ T log_domain_x1(T w0, T x1) {
     return (w0 < T(0) || isnan_(w0)) ? P<T>::qnan() : x1;
 }
 
-// tlog.  FAST: tlog_fast_arg (y0 and y0 + y1 positive and finite).
+// tlog.  FAST: tlog_fast_arg (y0 and y0 + y1 positive and finite, |y1| <= y0).
 template <bool FAST, class T>
 __device__ __forceinline__ void tlog_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o, T& x1o) {
     T x0 = log1x<FAST>(y0, lt);
-    Tw<T> v = two_sum(y0, y1);
+    Tw<T> v = FAST ? fast_two_sum_pz(y0, y1) : two_sum(y0, y1);
     int n;
     Tw<T> z = log_scale(v, n);
     Tw<T> a = {z.x0 - T(1), z.x1};                    // exact
@@ -642,13 +655,14 @@ __device__ __forceinline__ void tlog_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt
     }
 }
 
-// tlog1p.  FAST: tlog1p_fast_arg (y0 and y0 + y1 above -1 and finite).
+// tlog1p.  FAST: tlog1p_fast_arg (y0 and y0 + y1 above -1 and finite,
+// |y1| <= |y0|).
 template <bool FAST, class T>
 __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o,
                                             T& x1o) {
     using K = P<T>;
     T x0 = log1p_1x<FAST>(y0, lt);
-    Tw<T> v = two_sum(y0, y1);
+    Tw<T> v = FAST ? fast_two_sum_pz(y0, y1) : two_sum(y0, y1);
     bool outer = v.x0 < T(-0.5) || v.x0 > T(1);
     Tw<T> a = v;
     Tw<T> w = v;
