@@ -278,7 +278,10 @@ template <bool FAST, class T> __device__ __forceinline__ T expm1_1x(T x, ExpTab<
     Tw<T> A = two_sum(s.x, -fldexp(T(1), -m));
     Tw<T> B = two_prod(s.x, rhi);
     T c = ffma(s.x, plo, ffma(s.y, rhi, s.y));
-    Tw<T> H = two_sum(A.x0, B.x0);
+    // |A0| = |2^(j/32) - 2^-m| is 0 or at least 2^(1/32) - 1 = 0.02190, while
+    // |B0| = |2^(j/32) rhi| <= 2^(31/32) ln2/64 = 0.02120: a fast two-sum, with
+    // two_sum's bits
+    Tw<T> H = fast_two_sum_pz(A.x0, B.x0);
     T tail = H.x1 + ((A.x1 + B.x1) + c);
     T res = fldexp(H.x0 + tail, m);
     res = (fabs_(x) < K::EXPM1_TINY) ? expm1_tiny(x) : res;
