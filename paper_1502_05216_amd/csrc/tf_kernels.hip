@@ -10,8 +10,8 @@
 // straight-line fast body; any other wave runs the general body with the edge
 // handling.  The rare branch of texpm1 (|x0| > ln 2: pexp0(x0) - 1) does not
 // hold the fast body back: such lanes go to a per-wave LDS queue that is
-// drained with full waves.  tlog1p's outer branch (the log of 1 + y) is short
-// and runs under a wave vote inside the fast body.
+// drained with full waves.  tlog1p's outer branch (the log of 1 + y) runs
+// under a wave vote inside the fast body.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
