@@ -139,3 +139,45 @@ def test_autotune_picks_a_candidate_with_plain_results(tf):
         plan.launch()
         torch.cuda.synchronize()
     _check_equal(items, outs, plain)
+
+
+@pytest.mark.parametrize("config", [None, (1, 2, 1, 0), (4, 4, 8, 2)])
+def test_batch_with_fully_deferred_texpm1(tf, config):
+    """texpm1 arrays whose every lane has |x0| > ln 2 fill the per-wave queue on
+    every tile; interleaved with the other functions and formats, the queue of
+    the pair being left must be drained before the next pair's work, and the
+    drained z1 rewrites must land after the whole-line stores: the batch still
+    equals the plain calls bit for bit, on every replay."""
+    from paper_1502_05216_amd.batch import BatchPlan
+    d = torch.device("cuda:0")
+    rng = np.random.default_rng(21)
+    items, outs = [], []
+    for k in range(24):
+        fn = ("texpm1", "tlog1p", "texpm1", "texp", "tlog", "texpm1")[k % 6]
+        dt = np.float64 if k % 4 != 3 else np.float32
+        n = int(rng.integers(1, 30000))
+        if fn == "texpm1":
+            hi = 700.0 if dt == np.float64 else 85.0
+            lo = 40.0 if dt == np.float64 else 20.0
+            x0 = np.where(rng.random(n) < 0.5, rng.uniform(0.7, hi, n),
+                          -rng.uniform(0.7, lo, n)).astype(dt)
+            x1 = (x0 * rng.uniform(-1, 1, n).astype(dt) * np.finfo(dt).eps).astype(dt)
+        else:
+            x0, x1 = workloads.twofold_inputs(fn, n, dt, seed=100 + k)
+        a0 = torch.from_numpy(x0).to(d)
+        a1 = torch.from_numpy(x1).to(d)
+        z0 = torch.full_like(a0, float("nan"))
+        z1 = torch.full_like(a0, float("nan"))
+        items.append((fn, a0, a1, z0, z1))
+        outs.append((z0, z1))
+    plain = _plain(tf, items)
+    print("case deferred batch", config, flush=True)
+    with BatchPlan(items, config) as plan:
+        for r in range(3):
+            for _, _, _, z0, z1 in items:
+                z0.fill_(float("nan"))
+                z1.fill_(7.0)
+            torch.cuda.synchronize()
+            plan.launch()
+            torch.cuda.synchronize()
+            _check_equal(items, outs, plain)
