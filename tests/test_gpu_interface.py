@@ -111,3 +111,33 @@ def test_full_size_sampled(tf, dt):
         g0, g1 = on_gpu(tf, name, x0, x1)
         o0, o1 = on_oracle(name, dt, x0[idx], x1[idx])
         compare(g0[idx], g1[idx], o0, o1, "%s %s full-size sample" % (name, np.dtype(dt).name))
+
+
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+@pytest.mark.parametrize("name", DOTTED + COUPLED)
+def test_fast_and_general_bodies_agree(tf, name, dt):
+    """Ordinary arguments give the same bits on a fast wave and on a general
+    one: the same inputs run as they are and with one NaN in every 64 elements
+    (the argument of a dotted function, the second part of a coupled one),
+    which sends every wave to the general body."""
+    from parity_util import same_bits
+    n = 256 * 4 * 24 + 45
+    x0, x1 = inputs(name, n, dt, 95, 0.0)
+    print("case", name, np.dtype(dt).name, flush=True)
+    a0, a1 = on_gpu(tf, name, x0, x1)
+    rng = np.random.default_rng(96)
+    starts = np.arange(0, n, 64)
+    idx = starts + rng.integers(0, 64, size=starts.size)
+    idx = idx[idx < n]
+    p0, p1 = x0.copy(), x1.copy()
+    if name in DOTTED:
+        p0[idx] = np.nan
+    else:
+        p1[idx] = np.nan
+    b0, b1 = on_gpu(tf, name, p0, p1)
+    keep = np.ones(n, bool)
+    keep[idx] = False
+    for part, a, b in (("z0", a0, b0), ("z1", a1, b1)):
+        ok = same_bits(a[keep], b[keep])
+        assert ok.all(), "%s %s: %s differs at %d elements" % (name, np.dtype(dt).name, part,
+                                                               (~ok).sum())
