@@ -586,23 +586,14 @@ __device__ __forceinline__ T texpm1_big_fast(T x0, T x1, T z0, Pexp0Tab<T> pt) {
 // close to a/(1 + a) and s = e^-r0 - 1 close to -a/(1 + a): their magnitudes
 // agree to a few ulps, or both are so small that every sum is exact.  So
 // m0 + s0 is exact (Sterbenz), the two-sum of m + s has error 0, and its
-// twofold reduces to the two sums below, bit for bit.  The sum a s + a is a
-// fast two-sum with a first: |a s| is about a^2/(1 + a), at most |a|/2 for
-// a > 0 and below |a| for -1/2 < a < 0; only within a few ulps of a = -1/2
-// can the computed a s pass |a|, and there both have one sign and nearly one
-// magnitude.  In every case a0 - (a0 + (a s)0) is exact, so fast_two_sum_pz
-// gives two_sum's error, signed zeros included.
+// twofold reduces to the two sums below, bit for bit.  The sum a s + a keeps
+// the full two-sum: |a s| can reach |a| from below at a = -1/2 (a just under
+// 1/2 in magnitude, a s rounded up to 1/2), and there no three-operation sum
+// is exact.
 template <bool FAST, class T>
 __device__ __forceinline__ Tw<T> newton_seeded(Tw<T> a, T r0, Pm1Tab<T> mt) {
     Tw<T> s = pexpm10_small<FAST>(-r0, mt);
-    Tw<T> p = mul_tt(a, s);
-    Tw<T> m;
-    if constexpr (FAST) {
-        Tw<T> st = fast_two_sum_pz(a.x0, p.x0);
-        m = {st.x0, st.x1 + (p.x1 + a.x1)};
-    } else {
-        m = add_tt(p, a);
-    }
+    Tw<T> m = add_tt(mul_tt(a, s), a);
     T r1;
     if constexpr (FAST) {
         r1 = (m.x0 + s.x0) + (m.x1 + s.x1);
