@@ -162,8 +162,8 @@ template <class T> Tw<T> fast_two_sum(T a, T b) {
     T t = b - (s - a);
     return {s, t};
 }
-/* s + t = a + b exactly, any a, b (the corrected "Algorithm 2.2" of the
- * section "Twofold bugs", written for a + b). */
+/* s + t = a + b exactly, any a, b (Knuth's six-operation TwoSum: the sum,
+ * the parts of it attributed to b and to a, and their rounding errors). */
 template <class T> Tw<T> two_sum(T a, T b) {
     T s = a + b;
     T bp = s - a;
@@ -178,11 +178,13 @@ template <class T> Tw<T> two_prod(T a, T b) {
     T e = fma(a, b, -p);
     return {p, e};
 }
-/* twofold x dotted: main part is the 1x product; the low product is fused
- * into the error term (the FMA form of the paper's "2 mul + 1 FMA + 1 add"). */
+/* twofold x dotted, as the paper counts it (section "Twofold exponent:
+ * Method summary": 2 multiplications, 1 FMA and 1 summation): the exact
+ * product of the main parts, then the low product A1 c rounded on its own and
+ * added to the product's error. */
 template <class T> Tw<T> mul_td(Tw<T> A, T c) {
     Tw<T> pe = two_prod(A.x0, c);
-    return {pe.x0, fma(A.x1, c, pe.x1)};
+    return {pe.x0, pe.x1 + A.x1 * c};
 }
 /* twofold + dotted when |c| >= |A0| (the Horner coefficients dominate). */
 template <class T> Tw<T> add_td_fast(Tw<T> A, T c) {
@@ -775,17 +777,14 @@ template <class T> T tlog1pp(T y0, T y1, T* x1out) {
 /* z = x op y for twofolds x = x0 + x1, y = y0 + y1.  The main part is the    */
 /* 1x operation on the main parts; z1 carries the twofold error term.  The    */
 /* definitions are those of the twofold primitives above; subtraction is the  */
-/* corrected Algorithm 2.2 of section "Twofold bugs" as printed (for a - b).  */
+/* exact difference of the corrected subtraction of section "Twofold bugs".   */
 /* After the operation, the rule for a non-finite main part.                  */
 /* ------------------------------------------------------------------------ */
-template <class T> Tw<T> two_diff(T a, T b) {
-    T d = a - b;
-    T bp = d - a;
-    T ap = d - bp;
-    T bs = b + bp;
-    T as = a - ap;
-    return {d, as - bs};
-}
+/* d + t = a - b exactly: negation is exact, so the two-sum of a and -b is an
+ * error-free difference; its operations are those of the corrected
+ * subtraction of section "Twofold bugs", with the same results (x + (-y) and
+ * x - y are the same IEEE operation). */
+template <class T> Tw<T> two_diff(T a, T b) { return two_sum(a, -b); }
 
 template <class T> Tw<T> rule_tw(Tw<T> z) { return {z.x0, special_rule(z.x0, z.x1)}; }
 

@@ -48,9 +48,26 @@ def _run(cmd, verbose):
         print(out)
 
 
-def build(verbose=False, extra=()):
+# Flagged build variants of the same sources: name -> extra defines.
+#   horner2x: every Horner step of pexp0 and pexpm10 in twofold arithmetic
+#             (the algorithm listings' scheme; the default library runs the
+#             highest-degree steps in 1x, as the paper's cost discussion allows)
+VARIANTS = {
+    "horner2x": ["-DTF_HORNER_1X_TAIL=0"],
+}
+
+
+def variant_path(name):
+    """Path of the shared library of build variant `name`."""
+    if name not in VARIANTS:
+        raise ValueError("unknown variant %r" % (name,))
+    return os.path.join(PKG, "libtwofold_hip_%s.so" % name)
+
+
+def build(verbose=False, extra=(), out=None):
     """Compile the library (always recompiles: one object per source, in
     parallel, then the shared-library link) and return its path."""
+    out = out or LIB
     tmpdir = tempfile.mkdtemp(prefix="tf_build_")
     try:
         objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
@@ -59,13 +76,26 @@ def build(verbose=False, extra=()):
         with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
             for f in [ex.submit(_run, c, verbose) for c in cmds]:
                 f.result()
-        tmp = LIB + ".tmp"
+        tmp = out + ".tmp"
         _run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp],
              verbose)
-        os.replace(tmp, LIB)
+        os.replace(tmp, out)
     finally:
         shutil.rmtree(tmpdir, ignore_errors=True)
-    return LIB
+    return out
+
+
+def build_variant(name, verbose=False):
+    """Compile build variant `name` of the library; return its path."""
+    return build(verbose=verbose, extra=VARIANTS[name], out=variant_path(name))
+
+
+def build_all(verbose=False):
+    """The library and every build variant, concurrently."""
+    jobs = [lambda: build(verbose=verbose)] + [
+        (lambda n=n: build_variant(n, verbose=verbose)) for n in VARIANTS]
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        return [f.result() for f in [ex.submit(j) for j in jobs]]
 
 
 def _code_only(text):
@@ -93,4 +123,4 @@ def source_hash():
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build_all(verbose=True))

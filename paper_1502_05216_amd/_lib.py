@@ -35,13 +35,32 @@ class TwofoldError(RuntimeError):
         super().__init__("%s: %s (status %d)" % (what, msg, status))
 
 
+_variants = {}
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libtwofold_hip.so is not built (run __graft_entry__.build())")
-    lib = ctypes.CDLL(LIB_PATH)
+    _lib = _open(LIB_PATH)
+    return _lib
+
+
+def variant(name):
+    """The ctypes handle of build variant `name` of the library (the same C ABI
+    compiled with other defines; see _build.VARIANTS).  Pass it as `lib=` to
+    twofold_call / dotted_call."""
+    if name not in _variants:
+        from . import _build
+        _variants[name] = _open(_build.variant_path(name))
+    return _variants[name]
+
+
+def _open(path):
+    if not os.path.exists(path):
+        raise RuntimeError("%s is not built (run __graft_entry__.build())"
+                           % os.path.basename(path))
+    lib = ctypes.CDLL(path)
     P, S = ctypes.c_void_p, ctypes.c_size_t
     for f in TWOFOLD + COUPLED:
         for sfx in ("", "f"):
@@ -86,7 +105,6 @@ def _load():
     lib.tf_status_string.restype = ctypes.c_char_p
     lib.tf_version.restype = ctypes.c_char_p
     lib.tf_abi_version.restype = ctypes.c_int
-    _lib = lib
     return lib
 
 
@@ -132,9 +150,9 @@ def _validate(*ts):
             raise ValueError("twofold arrays must be contiguous")
 
 
-def twofold_call(name, x0, x1, out=None):
+def twofold_call(name, x0, x1, out=None, lib=None):
     """z0, z1 = name(x0 + x1) elementwise; name in TWOFOLD or COUPLED, or tsqrt
-    or trenorm."""
+    or trenorm.  `lib`: a variant's handle (default: the library)."""
     import torch
     if name not in TWOFOLD + COUPLED + ("tsqrt", "trenorm"):
         raise ValueError(name)
@@ -145,15 +163,16 @@ def twofold_call(name, x0, x1, out=None):
     else:
         z0, z1 = out
         _validate(x0, z0, z1)
-    fn = getattr(_load(), "tf_" + name + _suffix(x0))
+    fn = getattr(lib or _load(), "tf_" + name + _suffix(x0))
     with torch.cuda.device(x0.device):
         _check(fn(x0.data_ptr(), x1.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(),
                   _stream()), "tf_" + name)
     return z0, z1
 
 
-def dotted_call(name, x0, out=None):
-    """z0, z1 = name(x0) elementwise for a dotted argument; name in DOTTED."""
+def dotted_call(name, x0, out=None, lib=None):
+    """z0, z1 = name(x0) elementwise for a dotted argument; name in DOTTED.
+    `lib`: a variant's handle (default: the library)."""
     import torch
     if name not in DOTTED:
         raise ValueError(name)
@@ -164,7 +183,7 @@ def dotted_call(name, x0, out=None):
     else:
         z0, z1 = out
         _validate(x0, z0, z1)
-    fn = getattr(_load(), "tf_" + name + _suffix(x0))
+    fn = getattr(lib or _load(), "tf_" + name + _suffix(x0))
     with torch.cuda.device(x0.device):
         _check(fn(x0.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(), _stream()),
                "tf_" + name)

@@ -141,9 +141,14 @@ template <class T> __device__ __forceinline__ Tw<T> two_prod(T a, T b) {
     T p = a * b;
     return {p, ffma(a, b, -p)};
 }
+// Twofold times 1x with the operations the paper counts for it (section
+// "Twofold exponent / Method summary": two multiplications, one FMA, one
+// sum): the low product is rounded on its own before it meets the error of
+// the exact product.  Fusing it into that error with a second FMA would save
+// an operation but change the second part's bits.
 template <class T> __device__ __forceinline__ Tw<T> mul_td(Tw<T> A, T c) {
     Tw<T> pe = two_prod(A.x0, c);
-    return {pe.x0, ffma(A.x1, c, pe.x1)};
+    return {pe.x0, pe.x1 + A.x1 * c};
 }
 template <class T> __device__ __forceinline__ Tw<T> add_td_fast(Tw<T> A, T c) {
     Tw<T> st = fast_two_sum(c, A.x0);
@@ -171,15 +176,9 @@ template <class T> __device__ __forceinline__ Tw<T> div_tt(Tw<T> A, Tw<T> B) {
     T q1 = ((r + A.x1) - q0 * B.x1) / B.x0;
     return {q0, q1};
 }
-// d + t = a - b exactly, any a, b (the corrected subtraction algorithm).
-template <class T> __device__ __forceinline__ Tw<T> two_diff(T a, T b) {
-    T d = a - b;
-    T bp = d - a;
-    T ap = d - bp;
-    T bs = b + bp;
-    T as = a - ap;
-    return {d, as - bs};
-}
+// d + t = a - b exactly, any a, b: negating b is exact, so the two-sum of a
+// and -b is an error-free difference (x + (-y) is the IEEE operation x - y).
+template <class T> __device__ __forceinline__ Tw<T> two_diff(T a, T b) { return two_sum(a, -b); }
 __device__ __forceinline__ double fsqrt(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float fsqrt(float a) { return __builtin_sqrtf(a); }
 template <class T> __device__ __forceinline__ Tw<T> sel(bool c, Tw<T> a, Tw<T> b) {
@@ -380,7 +379,14 @@ template <class T> struct Scaled { Tw<T> v; int k; };
 // pexp0's all-twofold scheme: there a last-bit change in pexp0's twofold
 // representation would move the renormalised second part by many of its own
 // ulps, while the all-twofold result is the paper's, bit for bit.
-template <class T, int N, int J0, int JT> __device__ __forceinline__ Tw<T> horner_fact(T y) {
+//
+// Build define TF_HORNER_1X_TAIL=0 turns the 1x steps off everywhere: every
+// Horner step is then twofold, as in the algorithm listings.
+#ifndef TF_HORNER_1X_TAIL
+#define TF_HORNER_1X_TAIL 1
+#endif
+template <class T, int N, int J0, int JT_> __device__ __forceinline__ Tw<T> horner_fact(T y) {
+    constexpr int JT = TF_HORNER_1X_TAIL ? JT_ : N - 1;
     constexpr int TOP = JT >= N - 1 ? N - 2 : JT - 1;   // first twofold step after the start
     Tw<T> p;
     if constexpr (JT >= N - 1) {

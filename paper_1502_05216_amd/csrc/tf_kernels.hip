@@ -1016,7 +1016,13 @@ const char* tf_status_string(tf_status s) {
     return "unknown status";
 }
 
-const char* tf_version(void) { return "twofold_hip 0.1 (gfx950)"; }
+const char* tf_version(void) {
+#if TF_HORNER_1X_TAIL
+    return "twofold_hip 0.2 (gfx950; Horner with 1x tails)";
+#else
+    return "twofold_hip 0.2 (gfx950; all-twofold Horner)";
+#endif
+}
 
 int tf_abi_version(void) { return 1; }
 

@@ -2,7 +2,8 @@
 
 Bar: z0 identical bit for bit (NaNs compared by class, payloads differ
 between machines); z1 within 4 ulp of the oracle's z1, where the ulp is
-max(ulp(z1_oracle), eps * ulp(z0_oracle)) so that z1 ~ 0 is handled; NaN and
+max(ulp(z1_oracle), u * ulp(z0_oracle)) with the unit roundoff u = 2^-53
+(binary32 2^-24), so that z1 ~ 0 is handled; NaN and
 infinity classes equal; signed zeros equal.  The GPU runs the same sequence of
 IEEE operations as the oracle, so z1 is expected to be identical too and the
 number of non-identical z1 is reported.
@@ -19,13 +20,18 @@ def same_bits(a, b):
     return (a.view(ui) == b.view(ui)) | (np.isnan(a) & np.isnan(b))
 
 
+def unit_roundoff(dt):
+    """2^-53 for binary64, 2^-24 for binary32 (half the machine epsilon)."""
+    return np.finfo(dt).eps / 2
+
+
 def z1_ok(g0, g1, o0, o1):
     dt = o1.dtype
-    eps = np.finfo(dt).eps
+    u = unit_roundoff(dt)
     ok = same_bits(g1, o1)
     fin = np.isfinite(o1) & np.isfinite(g1) & np.isfinite(o0)
     with np.errstate(over="ignore", invalid="ignore"):
-        tol = 4 * np.maximum(np.spacing(np.abs(o1)), eps * np.spacing(np.abs(o0)))
+        tol = 4 * np.maximum(np.spacing(np.abs(o1)), u * np.spacing(np.abs(o0)))
         close = np.abs(g1.astype(np.float64) - o1.astype(np.float64)) <= tol
     ok |= fin & close & ~((o1 == 0) & (g1 == 0) & (np.signbit(o1) != np.signbit(g1)))
     return ok

@@ -5,7 +5,7 @@ Sizes span many tiles (256 threads x 2 elements) and a ragged tail; the
 edge cases are empty, single-element and sub-wave arrays, every edge argument
 crossed with special second parts, and in-place calls.  The full-size case runs
 the 2^26-element arrays in the launch configuration the benchmark times and
-checks a random sample of indices against the oracle.
+checks every element against the oracle.
 """
 import numpy as np
 import pytest
@@ -140,14 +140,12 @@ def test_rejects_bad_arguments(tf):
 
 
 @pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
-def test_full_size_sampled(tf, dt):
-    """2^26 elements per function (the benchmark's arrays and launch), checked on
-    a random sample of 100000 indices against the oracle, and on every element
-    for the property that z0 is the 1x function of x0 bit for bit (the 1x
-    kernels are pinned against the oracle's 1x functions above)."""
+def test_full_size_every_element(tf, dt):
+    """2^26 elements per function (the benchmark's arrays, edges included, in
+    the launch configuration it times): every element against the oracle
+    (z0 bit for bit, z1 within the bar), and z0 against the 1x kernel."""
     n = 1 << 26
     d = torch.device("cuda:0")
-    rng = np.random.default_rng(99)
     onex = {"texp": "exp1x", "texpm1": "expm1_1x", "tlog": "log1x", "tlog1p": "log1p_1x"}
     it_ = torch.int64 if dt == np.float64 else torch.int32
     for fn in FUNCS:
@@ -160,12 +158,11 @@ def test_full_size_sampled(tf, dt):
         assert bool(same.all()), "%s: z0 differs from %s at %d elements" % (
             fn, onex[fn], int((~same).sum()))
         del X0, r0, same
-        idx = np.sort(rng.choice(n, 100000, replace=False))
-        idx = np.concatenate([idx, [0, n - 1]])
-        it = torch.from_numpy(idx).to(d)
-        s0 = g0[it].cpu().numpy()
-        s1 = g1[it].cpu().numpy()
+        s0 = g0.cpu().numpy()
+        s1 = g1.cpu().numpy()
         del g0, g1
         torch.cuda.empty_cache()
-        o0, o1 = getattr(oracle, fn + sfx(dt))(x0[idx], x1[idx], threads=8)
-        compare(s0, s1, o0, o1, "%s %s full-size sample" % (fn, np.dtype(dt).name))
+        o0, o1 = getattr(oracle, fn + sfx(dt))(x0, x1, threads=16)
+        nd = compare(s0, s1, o0, o1, "%s %s full size" % (fn, np.dtype(dt).name))
+        print("%s %s: z1 not bit-identical at %d of %d" % (fn, np.dtype(dt).name, nd, n),
+              flush=True)

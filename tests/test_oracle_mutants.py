@@ -18,7 +18,8 @@ from paper_1502_05216_amd import workloads
 SRC = open(oracle.SRC).read()
 
 MUTANTS = {
-    "mul_td sign": ("return {pe.x0, fma(A.x1, c, pe.x1)};", "return {pe.x0, fma(A.x1, c, -pe.x1)};"),
+    "mul_td sign": ("return {pe.x0, pe.x1 + A.x1 * c};", "return {pe.x0, pe.x1 - A.x1 * c};"),
+    "mul_td dropped low product": ("return {pe.x0, pe.x1 + A.x1 * c};", "return {pe.x0, pe.x1};"),
     "two_sum sign": ("return {s, da + db};", "return {s, da - db};"),
     "mul_tt dropped term": ("fma(A.x0, B.x1, fma(A.x1, B.x0, pe.x1))", "fma(A.x1, B.x0, pe.x1)"),
     "Horner dropped term": ("for (int j = K::N - 2; j >= 0; --j)", "for (int j = K::N - 2; j >= 1; --j)"),
@@ -46,7 +47,8 @@ MUTANTS = {
                          "z1 = ldexp((s.v.x0 - z0s), s.k);"),
     "p-function not renormalised": ("Tw<T> r = fast_two_sum(z0, z1);", "Tw<T> r = {z0, z1};"),
     # twofold arithmetic
-    "two_diff sign": ("T bs = b + bp;", "T bs = b - bp;"),
+    "two_diff sign": ("template <class T> Tw<T> two_diff(T a, T b) { return two_sum(a, -b); }",
+                      "template <class T> Tw<T> two_diff(T a, T b) { return two_sum(a, b); }"),
     "tdiv dropped y1": ("T q1 = ((r + A.x1) - q0 * B.x1) / B.x0;", "T q1 = (r + A.x1) / B.x0;"),
     "tsqrt remainder sign": ("T r = fma(-z0, z0, x.x0);", "T r = fma(z0, z0, -x.x0);"),
     "trenorm fast sum for any pair": ("Tw<T> r = rule_tw(two_sum(x0, x1));",
