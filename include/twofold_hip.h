@@ -47,7 +47,8 @@ typedef enum {
     TF_ELAUNCH = 2,     /* kernel launch or HIP runtime call failed */
     TF_ENOMEM = 3,      /* device allocation failed (batch plans only) */
     TF_EUNSUPPORTED = 4,
-    TF_ENODEV = 5       /* no HIP device visible */
+    TF_ENODEV = 5,      /* no HIP device visible */
+    TF_ECAPACITY = 6    /* beyond the static capacity of tf_batch_run_noalloc */
 } tf_status;
 
 /* --- twofold functions, binary64 --------------------------------------- */
@@ -309,6 +310,32 @@ tf_status tf_batch_plan_create(const tf_batch_desc* descs, size_t count,
 tf_status tf_batch_launch(tf_batch_plan* plan, void* stream);
 tf_status tf_batch_plan_destroy(tf_batch_plan* plan);
 tf_status tf_batch_plan_info(const tf_batch_plan* plan, size_t* chunks, size_t* elements);
+
+/* --- batched ragged launch that allocates nothing -----------------------
+ * For callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  One call does what
+ * tf_batch_plan_create + tf_batch_launch + tf_batch_plan_destroy do, with the
+ * same kernels and the same results bit for bit, but calls no hipMalloc,
+ * hipFree or other allocating routine: the descriptor table, chunk list and
+ * work counter live in a static device array of the library,
+ * TF_BATCH_NOALLOC_SCRATCH_BYTES on each GPU it runs on, held until the
+ * process ends.  descs (host memory, count entries) are validated as for
+ * tf_batch_plan_create, then copied into that array on `stream` and read
+ * before the call returns; config as for tf_batch_plan_create (NULL = the
+ * defaults).  The chunks run dearest (function, format) first.
+ * Limits: count <= TF_BATCH_NOALLOC_MAX_ARRAYS and at most
+ * TF_BATCH_NOALLOC_MAX_CHUNKS chunks of chunk_tiles * 256 * ept elements in
+ * all (about 10^9 binary64 elements at the default configuration); beyond
+ * them TF_ECAPACITY, with nothing enqueued.  Errors otherwise as for the
+ * plan: TF_EINVAL for a bad descriptor or configuration, TF_ELAUNCH when a
+ * copy or launch fails.  Every call on one GPU uses that GPU's one array and
+ * leaves the last call's contents in it: calls on one stream run in order,
+ * calls that overlap on one GPU (other streams, other threads) race. */
+#define TF_BATCH_NOALLOC_MAX_ARRAYS 8192
+#define TF_BATCH_NOALLOC_MAX_CHUNKS 65536
+#define TF_BATCH_NOALLOC_SCRATCH_BYTES 1376512
+tf_status tf_batch_run_noalloc(const tf_batch_desc* descs, size_t count,
+                               const tf_batch_config* config, void* stream);
 
 /* --- launch configuration (used by the autotuner) ----------------------
  * fn: 0 texp, 1 texpm1, 2 tlog, 3 tlog1p, 4 exp1x, 5 expm1_1x, 6 log1x,

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 LIB_PATH = os.path.join(PKG, "libtwofold_hip.so")
 HEADER = os.path.join(ROOT, "include", "twofold_hip.h")
 
-TF_OK, TF_EINVAL, TF_ELAUNCH, TF_ENOMEM, TF_EUNSUPPORTED, TF_ENODEV = range(6)
+TF_OK, TF_EINVAL, TF_ELAUNCH, TF_ENOMEM, TF_EUNSUPPORTED, TF_ENODEV, TF_ECAPACITY = range(7)
 
 TWOFOLD = ("texp", "texpm1", "tlog", "tlog1p")
 ONEX = ("exp1x", "expm1_1x", "log1x", "log1p_1x")

@@ -12,6 +12,8 @@ bit for bit, under every configuration.
 
     best, times = autotune(items)           # time every candidate configuration
     plan = BatchPlan(items, config=best)    # or config="tuned": the tune cache
+
+    run_noalloc(items)     # the same launch in one call that allocates nothing
 """
 import ctypes
 
@@ -54,35 +56,58 @@ def _bind(lib):
     lib.tf_batch_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t),
                                        ctypes.POINTER(ctypes.c_size_t)]
     lib.tf_batch_plan_info.restype = ctypes.c_int
+    lib.tf_batch_run_noalloc.argtypes = [ctypes.POINTER(BatchDesc), ctypes.c_size_t,
+                                         ctypes.POINTER(BatchConfig), P]
+    lib.tf_batch_run_noalloc.restype = ctypes.c_int
     lib._tf_batch_bound = True
     return lib
+
+
+def _descs(items):
+    import torch
+    descs, keep = [], []
+    for func, x0, x1, z0, z1 in items:
+        if func not in FUNC_IDS:
+            raise ValueError(func)
+        _lib._validate(x0, x1, z0, z1)
+        dt = {torch.float64: 0, torch.float32: 1}.get(x0.dtype)
+        if dt is None:
+            raise TypeError("batch arrays must be float64 or float32")
+        descs.append(BatchDesc(FUNC_IDS[func], dt, x0.numel(), x0.data_ptr(), x1.data_ptr(),
+                               z0.data_ptr(), z1.data_ptr()))
+        keep += [x0, x1, z0, z1]
+    return (BatchDesc * max(1, len(descs)))(*descs), len(descs), keep
+
+
+MAX_ARRAYS_NOALLOC = 8192      # TF_BATCH_NOALLOC_MAX_ARRAYS
+MAX_CHUNKS_NOALLOC = 65536     # TF_BATCH_NOALLOC_MAX_CHUNKS
+
+
+def run_noalloc(items, config=None):
+    """The batched launch of `items` in one call that allocates no device
+    memory (tf_batch_run_noalloc): the library's static per-GPU scratch holds
+    the descriptors, chunk list and work counter.  Enqueued on the current
+    stream; results equal a BatchPlan's with the same config bit for bit.
+    Calls that overlap on one GPU race on that scratch."""
+    lib = _bind(_lib.lib())
+    arr, count, _keep = _descs(items)
+    cfg = BatchConfig(*(config or DEFAULT_CONFIG))
+    _lib._check(lib.tf_batch_run_noalloc(arr, count, ctypes.byref(cfg), _lib._stream()),
+                "tf_batch_run_noalloc")
 
 
 class BatchPlan:
     def __init__(self, items, config=None):
         """items: iterable of (func, x0, x1, z0, z1); config: (ept64, ept32,
         chunk_tiles, blocks_per_cu) or None for the library defaults."""
-        import torch
         self._lib = _bind(_lib.lib())
-        self._keep = []
-        descs = []
-        for func, x0, x1, z0, z1 in items:
-            if func not in FUNC_IDS:
-                raise ValueError(func)
-            _lib._validate(x0, x1, z0, z1)
-            dt = {torch.float64: 0, torch.float32: 1}.get(x0.dtype)
-            if dt is None:
-                raise TypeError("batch arrays must be float64 or float32")
-            descs.append(BatchDesc(FUNC_IDS[func], dt, x0.numel(), x0.data_ptr(), x1.data_ptr(),
-                                   z0.data_ptr(), z1.data_ptr()))
-            self._keep += [x0, x1, z0, z1]
-        arr = (BatchDesc * max(1, len(descs)))(*descs)
+        arr, count, self._keep = _descs(items)
         if config == "tuned":
             from . import tune
             config = tune.batch_config()
         cfg = BatchConfig(*(config or DEFAULT_CONFIG))
         handle = ctypes.c_void_p()
-        _lib._check(self._lib.tf_batch_plan_create(arr, len(descs), ctypes.byref(cfg),
+        _lib._check(self._lib.tf_batch_plan_create(arr, count, ctypes.byref(cfg),
                                                    ctypes.byref(handle)), "tf_batch_plan_create")
         self._plan = handle
         self.config = tuple(config or DEFAULT_CONFIG)

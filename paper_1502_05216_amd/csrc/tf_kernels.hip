@@ -471,6 +471,80 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TF_BATCH
     if (cur >= 0) batch_drain(lds, q64, q32, cur);
 }
 
+// ----------------------------------------------------------------------------
+// Batched launch without allocation (tf_batch_run_noalloc): the plan's device
+// tables (descriptors, chunk list, work counter) live in one static device
+// array, `scratch`, of fixed size.  The host copies the caller's descriptors
+// into it; a one-workgroup planner kernel converts them and writes the chunk
+// list, and k_batch runs over it exactly as over a plan's tables.
+// ----------------------------------------------------------------------------
+constexpr size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaMaxArrays = TF_BATCH_NOALLOC_MAX_ARRAYS;
+constexpr size_t kNaMaxChunks = TF_BATCH_NOALLOC_MAX_CHUNKS;
+constexpr size_t kNaOffRaw = 256;  // [0, 256): the work counter
+constexpr size_t kNaOffDesc = kNaOffRaw + round256(kNaMaxArrays * sizeof(tf_batch_desc));
+constexpr size_t kNaOffChunk = kNaOffDesc + round256(kNaMaxArrays * sizeof(BatchDesc));
+constexpr size_t kNaBytes = kNaOffChunk + round256(kNaMaxChunks * sizeof(BatchChunk));
+static_assert(kNaBytes == TF_BATCH_NOALLOC_SCRATCH_BYTES, "scratch size stated in the header");
+
+// One copy per GPU; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that GPU (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+struct NaPlanArgs {
+    unsigned count;             // descriptors in scratch (<= kNaMaxArrays)
+    unsigned chunk_elems[2];    // elements per chunk: binary64, binary32
+    unsigned class_base[8];     // first chunk slot of each key func*2 + dtype
+};
+
+// Converts the raw descriptors and writes the chunk list: the chunks of each
+// key in descriptor order, from that key's first slot (the host orders the
+// keys dearest first and checked every bound: count, and the chunk total
+// that class_base partitions).  Thread t owns a contiguous run of
+// descriptors; an exclusive scan over the threads' per-key chunk counts gives
+// each run its slots.  Also clears the work counter.
+__global__ __launch_bounds__(kBlock) void k_batch_plan_noalloc(unsigned char* scr, NaPlanArgs a) {
+    const tf_batch_desc* raw = reinterpret_cast<const tf_batch_desc*>(scr + kNaOffRaw);
+    BatchDesc* descs = reinterpret_cast<BatchDesc*>(scr + kNaOffDesc);
+    BatchChunk* chunks = reinterpret_cast<BatchChunk*>(scr + kNaOffChunk);
+    __shared__ unsigned run[kBlock][8];
+    const unsigned t = threadIdx.x;
+    const unsigned seg = (a.count + kBlock - 1) / kBlock;
+    const unsigned i0 = t * seg < a.count ? t * seg : a.count;
+    const unsigned i1 = i0 + seg < a.count ? i0 + seg : a.count;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) run[t][k] = 0u;
+    for (unsigned i = i0; i < i1; ++i) {
+        const tf_batch_desc d = raw[i];
+        const uintptr_t bits = (uintptr_t)d.x0 | (uintptr_t)d.x1 | (uintptr_t)d.z0 |
+                               (uintptr_t)d.z1;
+        descs[i] = BatchDesc{d.func, d.dtype, (bits & 15u) == 0 ? 1 : 0, 0, d.n, d.x0, d.x1,
+                             d.z0, d.z1};
+        const size_t ce = a.chunk_elems[d.dtype];
+        run[t][d.func * 2 + d.dtype] += (unsigned)((d.n + ce - 1) / ce);
+    }
+    __syncthreads();
+    if (t < 8) {
+        unsigned next = a.class_base[t];
+        for (unsigned u = 0; u < kBlock; ++u) {
+            const unsigned c = run[u][t];
+            run[u][t] = next;
+            next += c;
+        }
+    }
+    __syncthreads();
+    for (unsigned i = i0; i < i1; ++i) {
+        const tf_batch_desc d = raw[i];
+        const size_t ce = a.chunk_elems[d.dtype];
+        const unsigned nch = (unsigned)((d.n + ce - 1) / ce);
+        const int key = d.func * 2 + d.dtype;
+        const unsigned off = run[t][key];
+        run[t][key] = off + nch;
+        for (unsigned k = 0; k < nch; ++k) chunks[off + k] = BatchChunk{i, k};
+    }
+    if (t == 0) *reinterpret_cast<unsigned*>(scr) = 0u;
+}
+
 template <class T, int F1>
 __device__ __forceinline__ T eval1(const Lds<T, true, false, false, true>& lds, T a) {
     if constexpr (F1 == F1_EXP) return exp1x<false>(a, lds.et());
@@ -831,6 +905,46 @@ tf_status batch_capture(tf_batch_plan* p, int cus, int bpc, unsigned chunk_tiles
     return st;
 }
 
+// This GPU's address of `scratch`, taken once per device with that device
+// current (each GPU holds its own copy of the array).
+std::atomic<unsigned char*> g_scratch[kMaxDev];
+
+tf_status noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return TF_ENODEV;
+    }
+    if (dev < 0 || dev >= kMaxDev) return TF_EUNSUPPORTED;
+    unsigned char* p = g_scratch[dev].load(std::memory_order_acquire);
+    if (p == nullptr) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || q == nullptr) {
+            (void)hipGetLastError();
+            return TF_ELAUNCH;
+        }
+        p = static_cast<unsigned char*>(q);
+        g_scratch[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return TF_OK;
+}
+
+template <int E64, int E32>
+tf_status noalloc_batch(unsigned char* scr, unsigned nchunks, int cus, int bpc,
+                        unsigned chunk_tiles, hipStream_t s) {
+    auto kern = k_batch<E64, E32>;
+    static int occ = 0;            // per instantiation; benign race (same value)
+    if (occ == 0) occ = blocks_per_cu(kern);
+    unsigned grid = (unsigned)cus * (unsigned)(bpc > 0 ? bpc : occ);
+    if (grid > nchunks) grid = nchunks;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s,
+                       reinterpret_cast<const BatchDesc*>(scr + kNaOffDesc),
+                       reinterpret_cast<const BatchChunk*>(scr + kNaOffChunk), nchunks,
+                       reinterpret_cast<unsigned*>(scr), chunk_tiles);
+    return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1004,6 +1118,67 @@ tf_status tf_batch_plan_info(const tf_batch_plan* plan, size_t* chunks, size_t* 
     return TF_OK;
 }
 
+tf_status tf_batch_run_noalloc(const tf_batch_desc* descs, size_t count,
+                               const tf_batch_config* config, void* stream) {
+    if (count > 0 && !descs) return TF_EINVAL;
+    tf_batch_config c = {2, 4, 32, 0};
+    if (config) c = *config;
+    if (!((c.ept64 == 2 && c.ept32 == 4) || (c.ept64 == 4 && c.ept32 == 4) ||
+          (c.ept64 == 1 && c.ept32 == 2)) ||
+        c.chunk_tiles < 1 || c.chunk_tiles > 4096 || c.blocks_per_cu < 0 || c.blocks_per_cu > 64)
+        return TF_EINVAL;
+    if (count > kNaMaxArrays) return TF_ECAPACITY;
+    // validate and count the chunks per key (no buffer: a pass over descs)
+    const size_t ce[2] = {(size_t)c.chunk_tiles * kBlock * c.ept64,
+                          (size_t)c.chunk_tiles * kBlock * c.ept32};
+    size_t per_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    size_t total = 0;
+    for (size_t i = 0; i < count; ++i) {
+        const tf_batch_desc& d = descs[i];
+        if (d.func < 0 || d.func > 3 || d.dtype < 0 || d.dtype > 1) return TF_EINVAL;
+        if (d.n > 0 && (!d.x0 || !d.x1 || !d.z0 || !d.z1)) return TF_EINVAL;
+        const size_t nch = d.n / ce[d.dtype] + (d.n % ce[d.dtype] != 0);
+        if (nch > kNaMaxChunks) return TF_ECAPACITY;
+        per_key[d.func * 2 + d.dtype] += nch;
+        total += nch;
+        if (total > kNaMaxChunks) return TF_ECAPACITY;
+    }
+    if (total == 0) return TF_OK;
+    int cus = 0;
+    tf_status st = device_cus(&cus);
+    if (st != TF_OK) return st;
+    unsigned char* scr = nullptr;
+    st = noalloc_scratch(&scr);
+    if (st != TF_OK) return st;
+    // keys dearest first by the cost of a full chunk, as the plan orders
+    // its chunks (ties: lower key first)
+    int order[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    auto full_cost = [&](int key) { return (double)ce[key & 1] * kCost[key >> 1][key & 1]; };
+    std::stable_sort(order, order + 8, [&](int a, int b) { return full_cost(a) > full_cost(b); });
+    NaPlanArgs a{};
+    a.count = (unsigned)count;
+    a.chunk_elems[0] = (unsigned)ce[0];
+    a.chunk_elems[1] = (unsigned)ce[1];
+    unsigned base = 0;
+    for (int j = 0; j < 8; ++j) {
+        a.class_base[order[j]] = base;
+        base += (unsigned)per_key[order[j]];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // the descriptors are read from host memory before this call returns
+    if (hipMemcpyAsync(scr + kNaOffRaw, descs, count * sizeof(tf_batch_desc),
+                       hipMemcpyHostToDevice, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return TF_ELAUNCH;
+    }
+    hipLaunchKernelGGL(k_batch_plan_noalloc, dim3(1), dim3(kBlock), 0, s, scr, a);
+    if (hipGetLastError() != hipSuccess) return TF_ELAUNCH;
+    const unsigned nch = (unsigned)total;
+    if (c.ept64 == 2) return noalloc_batch<2, 4>(scr, nch, cus, c.blocks_per_cu, c.chunk_tiles, s);
+    if (c.ept64 == 4) return noalloc_batch<4, 4>(scr, nch, cus, c.blocks_per_cu, c.chunk_tiles, s);
+    return noalloc_batch<1, 2>(scr, nch, cus, c.blocks_per_cu, c.chunk_tiles, s);
+}
+
 const char* tf_status_string(tf_status s) {
     switch (s) {
         case TF_OK: return "ok";
@@ -1012,6 +1187,7 @@ const char* tf_status_string(tf_status s) {
         case TF_ENOMEM: return "device allocation failed";
         case TF_EUNSUPPORTED: return "unsupported";
         case TF_ENODEV: return "no HIP device";
+        case TF_ECAPACITY: return "beyond the static capacity of tf_batch_run_noalloc";
     }
     return "unknown status";
 }
