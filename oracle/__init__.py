@@ -43,13 +43,16 @@ FUNCS_ARITH = ["tadd", "tsub", "tmul", "tdiv"]
 
 
 def build(verbose=False):
-    """Compile oracle/tfo.cpp into oracle/libtfo.so (always recompiles)."""
+    """Compile oracle/tfo.cpp into oracle/libtfo.so and the quad etalon
+    oracle/qref.c into oracle/libqref.so (always recompiles)."""
     cmd = ["g++"] + CXXFLAGS + [SRC, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)
     _libs.pop(LIB, None)
+    from . import qref              # the binary128 etalon of the accuracy tests
+    qref.build(verbose)
     return LIB
 
 

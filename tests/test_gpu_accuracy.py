@@ -7,7 +7,9 @@ random coupled arguments, binary64 2^-98 / 2^-95 (exp family) and 2^-93 (log
 family), binary32 2^-42 / 2^-38 and 2^-36; results whose second part is
 subnormal are held to the L0 bound plus one subnormal ulp.  Also the
 p-functions pexp0 and pexpm10 (renormalized): coupled, and within 2^-104
-(binary32 2^-45).
+(binary32 2^-45).  And the full acceptance protocol (tests/accept_util.py) on
+the kernels' results for a million arguments per function and format plus
+the edge grid, against the binary128 etalon.
 """
 import math
 
@@ -16,6 +18,8 @@ import pytest
 
 from oracle import mpref
 from paper_1502_05216_amd import workloads
+
+from accept_util import N_ACCEPT, assert_accepted, describe, edge_grid, measure
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -86,3 +90,22 @@ def test_gpu_p_functions_coupled_and_accurate(tf, f):
         worst = max(mpref.rel_error(a, b, mpref.exact(fn, xi)) for xi, a, b in zip(xs, v0, v1))
         print("%s %s: worst 2^%.1f" % (name, f, math.log2(worst)))
         assert worst <= 2.0 ** bound, (name, math.log2(worst))
+
+
+@pytest.mark.parametrize("f", ["D", "F"])
+@pytest.mark.parametrize("fn", ["texp", "texpm1", "tlog", "tlog1p"])
+def test_gpu_acceptance_million(tf, fn, f):
+    """The paper's protocol on the kernels' own results (the arguments of the
+    oracle's acceptance test: a million draws of the benchmark's laws with 0.1%
+    edges, then the edge grid), in the default launch configuration."""
+    dt = np.float64 if f == "D" else np.float32
+    print("case acceptance", fn, f, flush=True)
+    x0, x1 = workloads.twofold_inputs(fn, N_ACCEPT, dt, seed=101 + len(fn), edges=0.001)
+    g0, g1 = edge_grid(fn, dt)
+    x0 = np.concatenate([x0, g0])
+    x1 = np.concatenate([x1, g1])
+    z0, z1 = _gpu(tf, fn, x0, x1)
+    s = measure(fn, x0, x1, z0, z1)
+    print(describe(s))
+    assert s["measured"] > 0.8 * N_ACCEPT
+    assert_accepted(s)
