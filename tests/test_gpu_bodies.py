@@ -101,3 +101,76 @@ def test_texpm1_deferred_lanes_against_oracle(tf, dt, frac):
     g0, g1 = gpu_call(tf, "texpm1", x0, x1)
     o0, o1 = getattr(oracle, "texpm1" + ("" if dt == np.float64 else "f"))(x0, x1)
     compare(g0, g1, o0, o1, "texpm1 %s deferred %.1f" % (dts, frac))
+
+
+def _branch_point_args(fn, dt, n, seed):
+    """Ordinary arguments only, packed at the logs' branch points: tlog near
+    y0 = 1/2 and 2 (scaling on or off) and at powers of two (reduced a0 = -1/2);
+    tlog1p near y0 = -1/2 and 1 (outer branch on or off), near 0 and just above
+    -1.  Second parts coupled, zero of either sign, or half an ulp."""
+    rng = np.random.default_rng(seed)
+    if fn == "tlog":
+        centres = [0.5, 2.0] + [2.0 ** k for k in rng.integers(-120, 120, 6)]
+    else:
+        centres = [-0.5, 1.0, 0.0, -1.0]
+    per = n // len(centres) + 1
+    parts = []
+    for c in centres:
+        k = rng.integers(-2000, 2000, per)
+        v = np.full(per, c, dt)
+        tgt = np.where(k > 0, np.inf, -np.inf).astype(dt)
+        for _ in range(int(np.abs(k).max())):
+            v = np.where(k != 0, np.nextafter(v, tgt), v)
+            k = k - np.sign(k)
+        parts.append(v)
+    x0 = np.concatenate(parts)[:n].astype(dt)
+    if fn == "tlog":
+        x0 = np.abs(x0)
+        x0[x0 == 0] = dt(1.0)
+    else:
+        x0[x0 <= -1] = np.nextafter(dt(-1.0), dt(0.0))
+    rng.shuffle(x0)
+    u = np.finfo(dt).eps / 2
+    r = rng.uniform(-1, 1, n).astype(dt)
+    x1 = (x0 * r * dt(u)).astype(dt)
+    pick = rng.integers(0, 6, n)
+    x1[pick == 0] = dt(0.0)
+    x1[pick == 1] = dt(-0.0)
+    half = (np.spacing(np.abs(x0)) / 2).astype(dt)
+    x1 = np.where(pick == 2, np.where(r < 0, -half, half), x1).astype(dt)
+    # the argument stays inside the domain (tlog1p: above -1)
+    if fn == "tlog1p":
+        x1 = np.where(x0 < -0.75, np.abs(x1), x1).astype(dt)
+    return x0, x1
+
+
+@pytest.mark.parametrize("ept", [0, 1, 4], ids=["default", "ept1", "ept4"])
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+@pytest.mark.parametrize("fn", ["tlog", "tlog1p"])
+def test_fast_body_at_branch_points(tf, fn, dt, ept):
+    """Whole waves of ordinary arguments at the logs' branch points run the
+    fast body (its cheaper Newton sum, outer-branch sums and + n ln2); with
+    one NaN second part in every 64 elements the same arguments run the
+    general body.  Both must give the same bits, and meet the oracle's bar."""
+    import oracle
+    from paper_1502_05216_amd import _lib
+    from parity_util import compare
+    dts = "f64" if dt == np.float64 else "f32"
+    if ept:
+        _, bpc, pd = _lib.get_launch_config(fn, dts)
+        _lib.set_launch_config(fn, dts, ept, bpc, pd)
+    n = 256 * 4 * 24
+    x0, x1 = _branch_point_args(fn, dt, n, seed=95)
+    print("case branch points", fn, dts, "ept", ept or "default", flush=True)
+    a0, a1 = gpu_call(tf, fn, x0, x1)
+    o0, o1 = getattr(oracle, fn + ("" if dt == np.float64 else "f"))(x0, x1)
+    compare(a0, a1, o0, o1, "%s %s branch points (fast body)" % (fn, dts))
+    p1 = x1.copy()
+    p1[::64] = np.nan
+    b0, b1 = gpu_call(tf, fn, x0, p1)
+    keep = np.ones(n, bool)
+    keep[::64] = False
+    for name, a, b in (("z0", a0, b0), ("z1", a1, b1)):
+        ok = same_bits(a[keep], b[keep])
+        assert ok.all(), "%s %s: %s fast and general bodies differ at %d elements" % (
+            fn, dts, name, (~ok).sum())
