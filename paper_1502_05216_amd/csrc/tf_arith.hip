@@ -20,35 +20,6 @@ using namespace tfk;
 
 namespace {
 
-enum Op : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4, OP_RENORM = 5 };
-
-template <int OP, class T> __device__ __forceinline__ Tw<T> arith(Tw<T> x, Tw<T> y) {
-    Tw<T> z;
-    if constexpr (OP == OP_ADD) {
-        z = add_tt(x, y);
-    } else if constexpr (OP == OP_SUB) {
-        Tw<T> dt = two_diff(x.x0, y.x0);
-        z = {dt.x0, dt.x1 + (x.x1 - y.x1)};
-    } else if constexpr (OP == OP_MUL) {
-        z = mul_tt(x, y);
-    } else if constexpr (OP == OP_DIV) {
-        z = div_tt(x, y);
-    } else if constexpr (OP == OP_RENORM) {
-        // the renormalized twofold of exactly the same value: RN(x0 + x1) and
-        // the exact remainder, for any x0, x1 (where |x0| >= |x1| the fast
-        // renormalization gives these bits)
-        z = two_sum(x.x0, x.x1);
-    } else {
-        // z0 = sqrt(x0), r = x0 - z0^2 exactly (FMA), z1 = (r + x1) / (2 z0);
-        // at x0 = 0 the correction is 0
-        T z0 = fsqrt(x.x0);
-        T r = ffma(-z0, z0, x.x0);
-        T z1 = (r + x.x1) / (z0 + z0);
-        z = {z0, x.x0 == T(0) ? T(0) : z1};
-    }
-    return {z.x0, special_rule(z.x0, z.x1)};
-}
-
 // y0, y1 are not read for tsqrt and trenorm (they may be null).
 template <int OP> constexpr bool kUnary = OP == OP_SQRT || OP == OP_RENORM;
 
@@ -71,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_arith(const T* x0, const T* x1, cons
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             Tw<T> y = UNARY ? Tw<T>{T(0), T(0)} : Tw<T>{c.v[e], d.v[e]};
-            Tw<T> r = arith<OP>(Tw<T>{a.v[e], b.v[e]}, y);
+            Tw<T> r = arith_elem<OP>(Tw<T>{a.v[e], b.v[e]}, y);
             r0.v[e] = r.x0;
             r1.v[e] = r.x1;
         }
@@ -85,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_arith(const T* x0, const T* x1, cons
             const size_t i = rbase + off + e;
             if (i < n) {
                 Tw<T> y = UNARY ? Tw<T>{T(0), T(0)} : Tw<T>{y0[i], y1[i]};
-                Tw<T> r = arith<OP>(Tw<T>{x0[i], x1[i]}, y);
+                Tw<T> r = arith_elem<OP>(Tw<T>{x0[i], x1[i]}, y);
                 z0[i] = r.x0;
                 z1[i] = r.x1;
             }

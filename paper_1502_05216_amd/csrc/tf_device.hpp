@@ -715,6 +715,45 @@ __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> 
 }
 
 // ----------------------------------------------------------------------------
+// Twofold arithmetic (section "Twofolds update"): z = x op y (tadd, tsub,
+// tmul, tdiv), z = sqrt(x) (tsqrt) and the renormalization of x (trenorm).  The
+// main part is the 1x operation on the main parts (IEEE +, -, *, / and sqrt,
+// correctly rounded); the second part is the exact error of that operation
+// from an error-free transform (two_sum, the error-free difference, the FMA
+// product) or the FMA remainder of a quotient or square root, plus the
+// first-order terms of the low parts.  Then the rule for a non-finite main
+// part.  y is not read for tsqrt and trenorm.
+// ----------------------------------------------------------------------------
+enum ArithOp : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4, OP_RENORM = 5 };
+
+template <int OP, class T> __device__ __forceinline__ Tw<T> arith_elem(Tw<T> x, Tw<T> y) {
+    Tw<T> z;
+    if constexpr (OP == OP_ADD) {
+        z = add_tt(x, y);
+    } else if constexpr (OP == OP_SUB) {
+        Tw<T> dt = two_diff(x.x0, y.x0);
+        z = {dt.x0, dt.x1 + (x.x1 - y.x1)};
+    } else if constexpr (OP == OP_MUL) {
+        z = mul_tt(x, y);
+    } else if constexpr (OP == OP_DIV) {
+        z = div_tt(x, y);
+    } else if constexpr (OP == OP_RENORM) {
+        // the renormalized twofold of exactly the same value: RN(x0 + x1) and
+        // the exact remainder, for any x0, x1 (where |x0| >= |x1| the fast
+        // renormalization gives these bits)
+        z = two_sum(x.x0, x.x1);
+    } else {
+        // z0 = sqrt(x0), r = x0 - z0^2 exactly (FMA), z1 = (r + x1) / (2 z0);
+        // at x0 = 0 the correction is 0
+        T z0 = fsqrt(x.x0);
+        T r = ffma(-z0, z0, x.x0);
+        T z1 = (r + x.x1) / (z0 + z0);
+        z = {z0, x.x0 == T(0) ? T(0) : z1};
+    }
+    return {z.x0, special_rule(z.x0, z.x1)};
+}
+
+// ----------------------------------------------------------------------------
 // The other entry points of the paper's interface: functions of a dotted
 // argument x0 (x1 = 0) and of a coupled argument (x0 + x1 rounds to x0), and
 // the p-functions, whose results are renormalised fast to a coupled twofold.
