@@ -13,7 +13,9 @@ the batched launch over 4096 ragged arrays of mixed function and format
 against the per-array launches and the mix-weighted plain rate; the forward
 and backward chain tlog1p(texpm1(texp(x))) at 2^24; the other entry points of
 the paper's interface at 2^26; the twofold arithmetic (tadd, tsub, tmul, tdiv,
-tsqrt, trenorm) at 2^26; and the CPU oracle timed on the host cores.
+tsqrt, trenorm) at 2^26; texp on the small 65536-element workload, with the
+oracle timed on it at one thread and all threads; and the CPU oracle timed on
+the host cores over the step's arrays.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f32]
                     [--no-batch] [--no-chain] [--no-interface] [--no-arith]
@@ -114,6 +116,38 @@ def cpu_baseline(inputs64, min_seconds, core_sample):
                       "scalar oracle, OpenMP static schedule" % (passes, n),
             "seconds": t, "host_cpus": os.cpu_count(),
             "one_thread": {"sample": core_sample, "per_function": per_core}}
+
+
+def bench_small(tf, workloads, reps=200):
+    """texp on the small binary64 workload (65536 twofolds, x0 ~ U[-700, 700],
+    x1 = x0 u 2^-53, no edges): the launch-bound end of the range.  Average
+    duration of one launch over `reps` back-to-back launches (HIP events)."""
+    import torch
+    dev = torch.device("cuda:0")
+    a, b = workloads.cfg1_inputs()
+    x0 = torch.from_numpy(a).to(dev)
+    x1 = torch.from_numpy(b).to(dev)
+    o = (torch.empty_like(x0), torch.empty_like(x0))
+    ms = kernel_ms(lambda: tf.texp(x0, x1, out=o), (), reps, warm=20, windows=3)
+    n = a.size
+    return {"n": n, "us": ms * 1e3, "gelem_s": n / ms / 1e6,
+            "launches_timed": reps, "inputs": (a, b)}
+
+
+def cpu_small(a, b, runs=5):
+    """The oracle's texp on the small workload: median of `runs` passes on one
+    thread and on up to 16 threads."""
+    import oracle
+    res = {}
+    for label, th in (("one_thread", 1), ("all_threads", max(1, min(16, os.cpu_count() or 1)))):
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.texp(a, b, threads=th)
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[runs // 2]
+        res[label] = {"threads": th, "us": t * 1e6, "mops": a.size / t / 1e6}
+    return res
 
 
 def bench_batch(tf, workloads, per64, per32, reps):
@@ -388,6 +422,11 @@ def main():
             log("f32 %-7s %.3f ms  %.1f Gelem/s" % (fn, ms, per32[fn]["gelem_s"]))
             del x0, x1, o
 
+    log("small workload: texp, 65536 binary64 twofolds")
+    small = bench_small(tf, workloads)
+    small_in = small.pop("inputs")
+    log("small texp %.2f us  %.1f Gelem/s" % (small["us"], small["gelem_s"]))
+
     batch = None
     if not args.no_batch:
         log("batched launch: 4096 ragged arrays")
@@ -419,6 +458,12 @@ def main():
         cpu = cpu_baseline(host64, args.cpu_seconds, args.cpu_core_sample)
         log("cpu baseline %.4f Gelem/s on %d threads (%.1f s)" % (cpu["value"], cpu["cores"],
                                                                 cpu["seconds"]))
+        small["oracle"] = cpu_small(*small_in)
+        for k in ("one_thread", "all_threads"):
+            small["gpu_vs_oracle_" + k] = small["oracle"][k]["us"] / small["us"]
+        log("small texp oracle: %.0f us on 1 thread, %.0f us on %d threads"
+            % (small["oracle"]["one_thread"]["us"], small["oracle"]["all_threads"]["us"],
+               small["oracle"]["all_threads"]["threads"]))
 
     rec = {
         "metric": "Gelem/s per twofold fn (double & float) + % FP64 peak; batched vs plain, 1 GPU",
@@ -432,6 +477,7 @@ def main():
         "cpu_baseline": cpu,
         "per_function_f64": per64,
         "per_function_f32": per32,
+        "small_texp": small,
         "batched": batch,
         "fwd_bwd_chain": chain,
         "interface": iface,
