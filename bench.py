@@ -35,6 +35,15 @@ N = 1 << 26
 FUNCS = ("texp", "texpm1", "tlog", "tlog1p")
 PEAK_FP64_TFLOPS = 78.6          # MI355X dense FP64 vector, FMA = 2 flops
 PEAK_FP64_ISSUE_T = 39.3         # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one op per lane
+# binary32: the published FP32 vector peak counts packed FP32 (two operations
+# per lane per instruction): 256 x 4 x 16 x 2 x 2.4 GHz = 78.6 T lane-operations/s,
+# 157.3 TFLOP/s with an FMA as 2.  The kernels are built without packed FP32,
+# and plain FP32 arithmetic issues at the FP64 lane rate (a probe of long
+# independent FMA, add and mul chains measures 38 T lane-operations/s at the
+# clock under load), so 39.3 T is the ceiling of the code as built.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_ISSUE_T = 78.6
+PEAK_FP32_NONPACKED_T = 39.3
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_ELEM = {"f64": 32, "f32": 16}
 
@@ -327,6 +336,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU oracle time (whole passes over the step)")
     ap.add_argument("--cpu-core-sample", type=int, default=1 << 21)
+    ap.add_argument("--variant", default=None,
+                    help="time the step with a flagged build variant of the library "
+                         "(paper_1502_05216_amd/_build.py VARIANTS, e.g. k6)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (the functions are "
@@ -350,6 +362,16 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
+    if args.variant:
+        from paper_1502_05216_amd import _lib
+        vlib = _lib.variant(args.variant)
+        log("step timed with build variant %s: %s" % (args.variant, vlib.tf_version().decode()))
+
+        def call(fn, a, b, out):
+            return _lib.twofold_call(fn, a, b, out=out, lib=vlib)
+    else:
+        def call(fn, a, b, out):
+            return getattr(tf, fn)(a, b, out=out)
 
     def step(marks=None):
         # marks: one HIP event before the first launch and one after each
@@ -357,7 +379,7 @@ def main():
         if marks is not None:
             marks[0].record(stream)
         for k, fn in enumerate(FUNCS):
-            getattr(tf, fn)(dev64[fn][0], dev64[fn][1], out=out64[fn])
+            call(fn, dev64[fn][0], dev64[fn][1], out64[fn])
             if marks is not None:
                 marks[k + 1].record(stream)
 
@@ -387,13 +409,13 @@ def main():
                      "fp64_tflops": N * opc["f64"][fn]["flops"] / ms / 1e9,
                      "hbm_gbs": N * BYTES_PER_ELEM["f64"] / ms / 1e6}
         # the same kernel timed like the binary32 and batched launches below
-        w = kernel_ms(lambda: getattr(tf, fn)(dev64[fn][0], dev64[fn][1], out=out64[fn]), (), 10)
+        w = kernel_ms(lambda: call(fn, dev64[fn][0], dev64[fn][1], out64[fn]), (), 10)
         per64[fn]["windowed_gelem_s"] = N / w / 1e6
         log("f64 %-7s %.3f ms  %.1f Gelem/s (windowed %.1f)" % (fn, ms, per64[fn]["gelem_s"],
                                                               per64[fn]["windowed_gelem_s"]))
     dom = max(FUNCS, key=lambda f: per64[f]["ms"])
     ach = per64[dom]["fp64_tflops"]
-    traffic = traffic_for("f64_" + dom, N)
+    traffic = None if args.variant else traffic_for("f64_" + dom, N)
     roofline = {"bound": "alu", "kernel": "k_twofold<double,%s>" % dom, "achieved": ach,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
                 "traffic": traffic,
@@ -412,13 +434,14 @@ def main():
             x1 = torch.from_numpy(b).to(dev)
             o = (torch.empty_like(x0), torch.empty_like(x0))
             ms = kernel_ms(lambda: getattr(tf, fn)(x0, x1, out=o), (), 10)
-            # packed FP32 is not used, so binary32 issues at the FP64 lane rate:
-            # 39.3 T lane-operations/s (78.6 TFLOP/s counting an FMA as 2)
+            ops_s = N * opc["f32"][fn]["ops"] / (ms * 1e-3)
             per32[fn] = {"ms": ms, "gelem_s": N / ms / 1e6,
                          "fp32_tflops": N * opc["f32"][fn]["flops"] / ms / 1e9,
-                         "issue_frac": N * opc["f32"][fn]["ops"] / (ms * 1e-3)
-                         / (PEAK_FP64_ISSUE_T * 1e12),
-                         "hbm_gbs": N * BYTES_PER_ELEM["f32"] / ms / 1e6}
+                         "frac": N * opc["f32"][fn]["flops"] / ms / 1e9 / PEAK_FP32_TFLOPS,
+                         "issue_frac": ops_s / (PEAK_FP32_ISSUE_T * 1e12),
+                         "nonpacked_issue_frac": ops_s / (PEAK_FP32_NONPACKED_T * 1e12),
+                         "hbm_gbs": N * BYTES_PER_ELEM["f32"] / ms / 1e6,
+                         "hbm_frac": N * BYTES_PER_ELEM["f32"] / ms / 1e6 / PEAK_HBM_GBS}
             log("f32 %-7s %.3f ms  %.1f Gelem/s" % (fn, ms, per32[fn]["gelem_s"]))
             del x0, x1, o
 
@@ -473,6 +496,7 @@ def main():
         "config": {"workload": "texp+texpm1+tlog+tlog1p binary64 twofolds, 2^26 elements each "
                                "(SoA x0,x1 -> z0,z1), 0.1% edge arguments",
                    "n_per_function": N, "functions": list(FUNCS)},
+        "variant": args.variant,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_function_f64": per64,

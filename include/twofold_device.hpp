@@ -51,13 +51,13 @@ using tfh::Tw;
 template <class T> struct tabs;
 template <> struct tabs<double> {
     __device__ static tfh::ExpTab<double> et() { return {TFH_D_S}; }
-    __device__ static tfh::Pexp0Tab<double> pt() { return {TFH_D_E, TFH_D_EK, TFH_D_C}; }
+    __device__ static tfh::Pexp0Tab<double> pt() { return {TFH_D_E, TFH_D_EK, tfh::pexp0_c_table(0.0)}; }
     __device__ static tfh::Pm1Tab<double> mt() { return {TFH_D_CM1}; }
     __device__ static tfh::LogTab<double> lt() { return {TFH_D_LOG_INVC, TFH_D_LOG}; }
 };
 template <> struct tabs<float> {
     __device__ static tfh::ExpTab<float> et() { return {TFH_F_S}; }
-    __device__ static tfh::Pexp0Tab<float> pt() { return {TFH_F_E, TFH_F_EK, TFH_F_C}; }
+    __device__ static tfh::Pexp0Tab<float> pt() { return {TFH_F_E, TFH_F_EK, tfh::pexp0_c_table(0.0f)}; }
     __device__ static tfh::Pm1Tab<float> mt() { return {TFH_F_CM1}; }
     __device__ static tfh::LogTab<float> lt() { return {TFH_F_LOG_INVC, TFH_F_LOG}; }
 };

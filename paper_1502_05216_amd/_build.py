@@ -52,8 +52,14 @@ def _run(cmd, verbose):
 #   horner2x: every Horner step of pexp0 and pexpm10 in twofold arithmetic
 #             (the algorithm listings' scheme; the default library runs the
 #             highest-degree steps in 1x, as the paper's cost discussion allows)
+#   k6:       pexp0 with the finer decomposition K = 6 (|y| <= 2^-7, one
+#             Taylor term fewer, a C table of twice the entries), the
+#             rebalancing of table size against Horner length that the section
+#             "Function pexp0()" closes with; validated against the binary128
+#             etalon, not the oracle (whose parameters are the paper's)
 VARIANTS = {
     "horner2x": ["-DTF_HORNER_1X_TAIL=0"],
+    "k6": ["-DTF_PEXP0_K=6"],
 }
 
 

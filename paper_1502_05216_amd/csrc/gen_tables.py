@@ -9,6 +9,10 @@ and rounded with exact integer arithmetic (fractions):
   stored as a twofold (hi, lo), k integer; C = e^(n/32)/N! twofold;
   (L, N) = (2, 12) double, (1, 6) float; -744 <= 4m <= 708, -128 <= n <= 128
   (float -102 <= 2m <= 88, -64 <= n <= 64).
+* the pexp0 table of the finer decomposition (build variant k6, the
+  rebalancing of the section's closing remarks): K = 6, C6 = e^(n/64)/N6!
+  with N6 = 11 (float 5), -256 <= n <= 256 (float -128 <= n <= 128); E is
+  shared, since 2^L m is the same split.
 * pexpm10 (section "Function pexpm10()"): e^(n/128) - 1, -89 <= n <= 89, and
   the twofold 1/N! (N = 10 double, 5 float).
 * twofold ln 2 (n ln2 in plog).
@@ -124,6 +128,12 @@ def build(f):
         EK.append(k)
     t["E"], t["EK"] = E, EK
     t["C"] = [pair(exp_q(Fraction(n, 32)) / math.factorial(N), f) for n in range(-nmax, nmax + 1)]
+    # finer decomposition: K = 6 halves |y| to 2^-7, one Taylor term fewer
+    N6 = 11 if f == "D" else 5
+    nmax6 = 2 * nmax
+    t["int6"] = dict(K=6, N=N6, C_OFF=nmax6, C_CNT=2 * nmax6 + 1)
+    t["C6"] = [pair(exp_q(Fraction(n, 64)) / math.factorial(N6), f)
+               for n in range(-nmax6, nmax6 + 1)]
     t["CM1"] = [pair(exp_q(Fraction(n, 128)) - 1, f) for n in range(-89, 90)]
     t["S"] = [pair(exp_q(Fraction(j, 32) * LN2), f) for j in range(32)]
     scal = {}
@@ -195,13 +205,15 @@ def emit(tabs):
         P = "TFH_" + f + "_"
         for k, v in t["int"].items():
             o.append("#define %s%s %d" % (P, k, v))
+        for k, v in t["int6"].items():
+            o.append("#define %sK6_%s %d" % (P, k, v))
         for k, v in t["scal"].items():
             o.append("#define %s%s %s" % (P, k, lit(v, f)))
         o.append("#define %sEXP_NC %d" % (P, len(t["EXP_C"])))
         o.append("#define %sLOG_NC %d" % (P, len(t["LOG_C"])))
         o.append("#define %sEXP_C_LIST %s" % (P, ", ".join(lit(c, f) for c in t["EXP_C"])))
         o.append("#define %sLOG_C_LIST %s" % (P, ", ".join(lit(c, f) for c in t["LOG_C"])))
-        for name in ("E", "C", "CM1", "S", "LOG"):
+        for name in ("E", "C", "C6", "CM1", "S", "LOG"):
             arr = t[name]
             o.append("__device__ const %s %s%s[%d] = {" % (two, P, name, len(arr)))
             for i in range(0, len(arr), 2):

@@ -25,7 +25,7 @@ template <class T> struct G;
 template <> struct G<double> {
     __device__ static const double2* E() { return TFH_D_E; }
     __device__ static const int* EK() { return TFH_D_EK; }
-    __device__ static const double2* C() { return TFH_D_C; }
+    __device__ static const double2* C() { return pexp0_c_table(0.0); }
     __device__ static const double2* CM1() { return TFH_D_CM1; }
     __device__ static const double2* S() { return TFH_D_S; }
     __device__ static const double2* LOG() { return TFH_D_LOG; }
@@ -34,7 +34,7 @@ template <> struct G<double> {
 template <> struct G<float> {
     __device__ static const float2* E() { return TFH_F_E; }
     __device__ static const int* EK() { return TFH_F_EK; }
-    __device__ static const float2* C() { return TFH_F_C; }
+    __device__ static const float2* C() { return pexp0_c_table(0.0f); }
     __device__ static const float2* CM1() { return TFH_F_CM1; }
     __device__ static const float2* S() { return TFH_F_S; }
     __device__ static const float2* LOG() { return TFH_F_LOG; }

@@ -42,6 +42,17 @@ __device__ __forceinline__ bool isnan_(float a) { return __builtin_isnan(a); }
 // ----------------------------------------------------------------------------
 // Format parameters
 // ----------------------------------------------------------------------------
+// Build define TF_PEXP0_K selects pexp0's decomposition x = 2^L m + 2^-K n + y:
+// K = 5, the paper's parameters (default), or K = 6 (build variant k6, the
+// rebalancing the section "Function pexp0()" closes with): |y| <= 2^-7, so
+// the Taylor sum needs one term fewer (N = 11, binary32 5) and its twofold
+// part one step fewer, for a C table of twice the entries (8 KB in binary64).
+#ifndef TF_PEXP0_K
+#define TF_PEXP0_K 5
+#endif
+constexpr bool kPexp0K6 = TF_PEXP0_K == 6;
+static_assert(TF_PEXP0_K == 5 || TF_PEXP0_K == 6, "TF_PEXP0_K is 5 or 6");
+
 constexpr double fact_ratio(int n, int j) {  // n!/j!, exact for n <= 12
     double r = 1.0;
     for (int i = j + 1; i <= n; ++i) r *= i;
@@ -50,12 +61,22 @@ constexpr double fact_ratio(int n, int j) {  // n!/j!, exact for n <= 12
 
 template <class T> struct P;
 
+// pexp0's C table of the selected decomposition.
+__device__ __forceinline__ const double2* pexp0_c_table(double) {
+    return kPexp0K6 ? TFH_D_C6 : TFH_D_C;
+}
+__device__ __forceinline__ const float2* pexp0_c_table(float) {
+    return kPexp0K6 ? TFH_F_C6 : TFH_F_C;
+}
+
 template <> struct P<double> {
     using V2 = double2;
     using U = uint64_t;
-    static constexpr int L = TFH_D_L, K = TFH_D_K, N = TFH_D_N, N1 = TFH_D_N1;
+    static constexpr int L = TFH_D_L, N1 = TFH_D_N1;
+    static constexpr int K = kPexp0K6 ? TFH_D_K6_K : TFH_D_K, N = kPexp0K6 ? TFH_D_K6_N : TFH_D_N;
     static constexpr int E_OFF = TFH_D_E_OFF, E_CNT = TFH_D_E_CNT;
-    static constexpr int C_OFF = TFH_D_C_OFF, C_CNT = TFH_D_C_CNT;
+    static constexpr int C_OFF = kPexp0K6 ? TFH_D_K6_C_OFF : TFH_D_C_OFF;
+    static constexpr int C_CNT = kPexp0K6 ? TFH_D_K6_C_CNT : TFH_D_C_CNT;
     static constexpr int CM1_OFF = TFH_D_CM1_OFF, CM1_CNT = TFH_D_CM1_CNT;
     static constexpr int MANT = 52, EXPMASK = 0x7ff, BIAS = 1023, SUBSCALE = 54;
     static constexpr U MANT_MASK = 0x000fffffffffffffull;
@@ -71,8 +92,8 @@ template <> struct P<double> {
     static constexpr double EXP_XLO = TFH_D_EXP_XLO, EXPM1_XNEG = TFH_D_EXPM1_XNEG;
     static constexpr double EXPM1_TINY = TFH_D_EXPM1_TINY, LOG1P_TINY = TFH_D_LOG1P_TINY;
     // Highest Horner step run in twofold arithmetic (horner_fact): pexp0 with
-    // the 1x tail, pexpm10.
-    static constexpr int EXP_TF_J = 7, EXPM1_TF_J = 6;
+    // the 1x tail (|y| <= 2^-6, or 2^-7 with K = 6), pexpm10.
+    static constexpr int EXP_TF_J = kPexp0K6 ? 6 : 7, EXPM1_TF_J = 6;
     static constexpr int EXP_NC = TFH_D_EXP_NC, LOG_NC = TFH_D_LOG_NC;
     static constexpr double EXP_C[EXP_NC] = {TFH_D_EXP_C_LIST};
     static constexpr double LOG_C[LOG_NC] = {TFH_D_LOG_C_LIST};
@@ -84,9 +105,11 @@ template <> struct P<double> {
 template <> struct P<float> {
     using V2 = float2;
     using U = uint32_t;
-    static constexpr int L = TFH_F_L, K = TFH_F_K, N = TFH_F_N, N1 = TFH_F_N1;
+    static constexpr int L = TFH_F_L, N1 = TFH_F_N1;
+    static constexpr int K = kPexp0K6 ? TFH_F_K6_K : TFH_F_K, N = kPexp0K6 ? TFH_F_K6_N : TFH_F_N;
     static constexpr int E_OFF = TFH_F_E_OFF, E_CNT = TFH_F_E_CNT;
-    static constexpr int C_OFF = TFH_F_C_OFF, C_CNT = TFH_F_C_CNT;
+    static constexpr int C_OFF = kPexp0K6 ? TFH_F_K6_C_OFF : TFH_F_C_OFF;
+    static constexpr int C_CNT = kPexp0K6 ? TFH_F_K6_C_CNT : TFH_F_C_CNT;
     static constexpr int CM1_OFF = TFH_F_CM1_OFF, CM1_CNT = TFH_F_CM1_CNT;
     static constexpr int MANT = 23, EXPMASK = 0xff, BIAS = 127, SUBSCALE = 25;
     static constexpr U MANT_MASK = 0x007fffffu;

@@ -1193,7 +1193,9 @@ const char* tf_status_string(tf_status s) {
 }
 
 const char* tf_version(void) {
-#if TF_HORNER_1X_TAIL
+#if TF_HORNER_1X_TAIL && TF_PEXP0_K == 6
+    return "twofold_hip 0.2 (gfx950; Horner with 1x tails; pexp0 K=6)";
+#elif TF_HORNER_1X_TAIL
     return "twofold_hip 0.2 (gfx950; Horner with 1x tails)";
 #else
     return "twofold_hip 0.2 (gfx950; all-twofold Horner)";

@@ -4,12 +4,14 @@ include/twofold_hip.h declares, and validates arguments before any HIP call
 library's tables equal the oracle's, value for value -- two generators written
 independently (decimal vs mpmath) from the same definitions."""
 import ctypes
+import math
 import os
 import re
+from fractions import Fraction
 
 import pytest
 
-from tables_util import parse_header
+from tables_util import is_twofold_rn, parse_header
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1502_05216_amd", "libtwofold_hip.so")
@@ -101,6 +103,34 @@ def test_gpu_tables_equal_oracle_tables(f):
         assert h(k) == o(k), k
     for k in ("L", "K", "N", "N1", "E_OFF", "E_CNT", "C_OFF", "C_CNT", "CM1_OFF", "CM1_CNT"):
         assert h(k) == o(k), k
+
+
+@pytest.mark.parametrize("f", ["D", "F"])
+def test_k6_variant_table_against_mpmath(f):
+    """The C table of build variant k6 (pexp0 with K = 6): entry n is the
+    round-to-nearest twofold of e^(n/64)/N6!, N6 = 11 (binary32 5), for
+    |n| <= 256 (128), recomputed with mpmath at 240 bits; its sizes cover the
+    decomposition's n < 2^(L+K)."""
+    import mpmath
+    H = _hip_tables()
+    h = lambda k: H["TFH_%s_%s" % (f, k)]
+    p, emin = (53, -1022) if f == "D" else (24, -126)
+    assert h("K6_K") == 6 and h("K6_N") == (11 if f == "D" else 5)
+    assert h("K6_C_OFF") == 2 ** (h("L") + 6) and h("K6_C_CNT") == 2 * h("K6_C_OFF") + 1
+    c6 = h("C6")
+    assert len(c6) == 2 * h("K6_C_CNT")
+    with mpmath.workprec(240):
+        fact = mpmath.factorial(h("K6_N"))
+        for k, n in enumerate(range(-h("K6_C_OFF"), h("K6_C_OFF") + 1)):
+            man, ex = (mpmath.exp(mpmath.mpf(n) / 64) / fact).man_exp
+            v = Fraction(man) * Fraction(2) ** ex
+            assert is_twofold_rn(c6[2 * k], c6[2 * k + 1], v, p, emin), n
+    # the Taylor remainder of the shortened sum at |y| = 2^-7 stays far below
+    # the twofold precision of the format: 2^-112.8 <= 2^-108 (binary32
+    # 2^-51.5 <= 2^-50)
+    n6 = h("K6_N")
+    rem6 = Fraction(1, 2 ** (7 * (n6 + 1))) / math.factorial(n6 + 1)
+    assert rem6 <= Fraction(1, 2 ** (2 * p + 2))
 
 
 def test_batch_plan_validation(lib):
