@@ -130,6 +130,40 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+_entries = {}
+_raw_stream = None
+
+
+def _current_raw_stream(dev):
+    """torch's current stream on device `dev`, as the integer handle."""
+    global _raw_stream
+    if _raw_stream is None:
+        import torch
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        _raw_stream = raw if raw is not None else (
+            lambda d: torch.cuda.current_stream(d).cuda_stream)
+    return _raw_stream(dev)
+
+
+def _invoke(symbol, ref, args, lib=None):
+    """Calls entry point `symbol` with `args` and torch's current stream of the
+    device `ref` lives on, with that device current; raises on an error
+    status.  The entry points and the stream handle are looked up once per
+    call site's arguments, so a call costs a few microseconds of host time."""
+    import torch
+    lib = lib or _load()
+    key = (id(lib), symbol)
+    fn = _entries.get(key)
+    if fn is None:
+        fn = _entries[key] = getattr(lib, symbol)
+    dev = ref.get_device()
+    if dev == torch.cuda.current_device():
+        _check(fn(*args, _current_raw_stream(dev)), symbol)
+    else:
+        with torch.cuda.device(dev):
+            _check(fn(*args, _current_raw_stream(dev)), symbol)
+
+
 def _suffix(t):
     import torch
     if t.dtype == torch.float64:
@@ -163,10 +197,8 @@ def twofold_call(name, x0, x1, out=None, lib=None):
     else:
         z0, z1 = out
         _validate(x0, z0, z1)
-    fn = getattr(lib or _load(), "tf_" + name + _suffix(x0))
-    with torch.cuda.device(x0.device):
-        _check(fn(x0.data_ptr(), x1.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(),
-                  _stream()), "tf_" + name)
+    _invoke("tf_" + name + _suffix(x0), x0,
+            (x0.data_ptr(), x1.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel()), lib)
     return z0, z1
 
 
@@ -183,10 +215,8 @@ def dotted_call(name, x0, out=None, lib=None):
     else:
         z0, z1 = out
         _validate(x0, z0, z1)
-    fn = getattr(lib or _load(), "tf_" + name + _suffix(x0))
-    with torch.cuda.device(x0.device):
-        _check(fn(x0.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel(), _stream()),
-               "tf_" + name)
+    _invoke("tf_" + name + _suffix(x0), x0,
+            (x0.data_ptr(), z0.data_ptr(), z1.data_ptr(), x0.numel()), lib)
     return z0, z1
 
 
@@ -202,10 +232,9 @@ def arith_call(name, x0, x1, y0, y1, out=None):
     else:
         z0, z1 = out
         _validate(x0, z0, z1)
-    fn = getattr(_load(), "tf_" + name + _suffix(x0))
-    with torch.cuda.device(x0.device):
-        _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), z0.data_ptr(),
-                  z1.data_ptr(), x0.numel(), _stream()), "tf_" + name)
+    _invoke("tf_" + name + _suffix(x0), x0,
+            (x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), z0.data_ptr(),
+             z1.data_ptr(), x0.numel()))
     return z0, z1
 
 
@@ -216,9 +245,7 @@ def onex_call(name, x, out=None):
     _validate(x)
     z = torch.empty_like(x) if out is None else out
     _validate(x, z)
-    fn = getattr(_load(), "tf_" + name + _suffix(x))
-    with torch.cuda.device(x.device):
-        _check(fn(x.data_ptr(), z.data_ptr(), x.numel(), _stream()), "tf_" + name)
+    _invoke("tf_" + name + _suffix(x), x, (x.data_ptr(), z.data_ptr(), x.numel()))
     return z
 
 
@@ -236,10 +263,9 @@ def backward_call(name, s0, s1, g0, g1, out=None):
     else:
         gx0, gx1 = out
         _validate(s0, gx0, gx1)
-    fn = getattr(_load(), "tf_" + name + _suffix(s0) + "_bwd")
-    with torch.cuda.device(s0.device):
-        _check(fn(s0.data_ptr(), s1.data_ptr(), g0.data_ptr(), g1.data_ptr(), gx0.data_ptr(),
-                  gx1.data_ptr(), s0.numel(), _stream()), "tf_" + name + "_bwd")
+    _invoke("tf_" + name + _suffix(s0) + "_bwd", s0,
+            (s0.data_ptr(), s1.data_ptr(), g0.data_ptr(), g1.data_ptr(), gx0.data_ptr(),
+             gx1.data_ptr(), s0.numel()))
     return gx0, gx1
 
 

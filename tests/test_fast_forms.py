@@ -225,3 +225,4 @@ def test_plus_n_ln2_as_fast_two_sum(dt):
     f = (s, t + (x1 + L1))
     np.testing.assert_array_equal(bits(f[0]), bits(g[0]))
     np.testing.assert_array_equal(bits(f[1]), bits(g[1]))
+

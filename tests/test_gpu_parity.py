@@ -166,3 +166,33 @@ def test_full_size_every_element(tf, dt):
         nd = compare(s0, s1, o0, o1, "%s %s full size" % (fn, np.dtype(dt).name))
         print("%s %s: z1 not bit-identical at %d of %d" % (fn, np.dtype(dt).name, nd, n),
               flush=True)
+
+
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+def test_log1p_tiny_arguments(tf, dt):
+    """Arguments at and below the 1x log1p's tiny threshold (2^-60, binary32
+    2^-30), subnormals and signed zeros, in whole arrays (so tlog1p's waves
+    take the fast body): the 1x kernel, tlog1p and tlog1p0 against the oracle,
+    main parts bit for bit."""
+    rng = np.random.default_rng(23)
+    fi = np.finfo(dt)
+    n = 256 * 4 * 16
+    lo = np.log2(float(fi.smallest_subnormal))
+    x = (np.exp2(rng.uniform(lo, -20, n)) * np.where(rng.uniform(-1, 1, n) < 0, -1, 1)).astype(dt)
+    x[:6] = np.array([0.0, -0.0, fi.smallest_subnormal, -fi.smallest_subnormal,
+                      2.0 ** (-60 if dt == np.float64 else -30), -(2.0 ** (-60 if dt == np.float64 else -30))],
+                     dtype=dt)
+    x1 = (x * dt(fi.eps / 4)).astype(dt)
+    print("case log1p tiny", np.dtype(dt).name, flush=True)
+    d = torch.device("cuda:0")
+    g = tf.log1p_1x(torch.from_numpy(x).to(d))
+    torch.cuda.synchronize()
+    o = getattr(oracle, "log1p_1x" + sfx(dt))(x)
+    assert same_bits(g.cpu().numpy(), o).all()
+    g0, g1 = gpu_call(tf, "tlog1p", x, x1)
+    o0, o1 = getattr(oracle, "tlog1p" + sfx(dt))(x, x1)
+    compare(g0, g1, o0, o1, "tlog1p tiny %s" % np.dtype(dt).name)
+    h0, h1 = tf.tlog1p0(torch.from_numpy(x).to(d))
+    torch.cuda.synchronize()
+    p0, p1 = getattr(oracle, "tlog1p0" + sfx(dt))(x)
+    compare(h0.cpu().numpy(), h1.cpu().numpy(), p0, p1, "tlog1p0 tiny %s" % np.dtype(dt).name)
