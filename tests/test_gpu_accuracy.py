@@ -109,3 +109,26 @@ def test_gpu_acceptance_million(tf, fn, f):
     print(describe(s))
     assert s["measured"] > 0.8 * N_ACCEPT
     assert_accepted(s)
+
+
+@pytest.mark.parametrize("f", ["D", "F"])
+@pytest.mark.parametrize("name", workloads.DOTTED + workloads.COUPLED)
+def test_gpu_acceptance_interface_functions(tf, name, f):
+    """The other 16 entry points' kernels under the same protocol, on the
+    arguments of the oracle's acceptance test of them."""
+    dt = np.float64 if f == "D" else np.float32
+    print("case acceptance", name, f, flush=True)
+    iface = workloads.DOTTED + workloads.COUPLED
+    base = workloads.INTERFACE_BASE[name]
+    dotted = name in workloads.DOTTED
+    x0, x1 = workloads.twofold_inputs(name, N_ACCEPT, dt, seed=201 + iface.index(name),
+                                      edges=0.001, coupled=not dotted)
+    if dotted:
+        x1 = np.zeros_like(x0)
+        z0, z1 = _gpu(tf, name, x0)
+    else:
+        z0, z1 = _gpu(tf, name, x0, x1)
+    s = measure(base, x0, x1, z0, z1)
+    print(name, describe(s))
+    assert s["measured"] > 0.8 * N_ACCEPT
+    assert_accepted(s)

@@ -58,6 +58,32 @@ def test_acceptance_million(fn, fmt):
     assert_accepted(s)
 
 
+IFACE = workloads.DOTTED + workloads.COUPLED
+
+
+@pytest.mark.parametrize("fmt", ["D", "F"])
+@pytest.mark.parametrize("name", IFACE)
+def test_acceptance_interface_functions(name, fmt):
+    """The other 16 entry points under the same protocol: the dotted-argument
+    functions on a million x0 (second part 0), the coupled-argument ones on a
+    million coupled twofolds (x1 = x0 u 2^-54), each with its family's bars."""
+    dt = np.float64 if fmt == "D" else np.float32
+    sfx = "f" if fmt == "F" else ""
+    base = workloads.INTERFACE_BASE[name]
+    dotted = name in workloads.DOTTED
+    x0, x1 = workloads.twofold_inputs(name, N_ACCEPT, dt, seed=201 + IFACE.index(name),
+                                      edges=0.001, coupled=not dotted)
+    if dotted:
+        x1 = np.zeros_like(x0)
+        z0, z1 = getattr(oracle, name + sfx)(x0, threads=oracle.default_threads())
+    else:
+        z0, z1 = getattr(oracle, name + sfx)(x0, x1, threads=oracle.default_threads())
+    s = measure(base, x0, x1, z0, z1)
+    print(name, describe(s))
+    assert s["measured"] > 0.8 * N_ACCEPT
+    assert_accepted(s)
+
+
 def test_acceptance_catches_a_planted_mistake():
     """The protocol is sharp enough to see a one-ulp slip in the second part:
     z1 moved by 2^-50 of z0 on one element in 2^12 gives L1 far above 2^-98."""
