@@ -119,12 +119,24 @@ def cpu_baseline(inputs64, min_seconds, core_sample):
         getattr(oracle, fn)(a0, a1, threads=1)
         per_core[fn] = {"mops": core_sample / (time.perf_counter() - t0) / 1e6,
                         "paper_mops": PAPER_MOPS_PER_CORE[fn]}
+    # context: the comparison systems of the paper's performance table, one
+    # thread, on the same arguments: libquadmath (expq ...) and the C library
+    from oracle import qref
+    context = {}
+    for fn in FUNCS:
+        x = np.ascontiguousarray(inputs64[fn][0][:1 << 16])
+        xs = x[np.isfinite(x)]
+        q = qref.context_mops(fn, xs, quad=True)
+        c = qref.context_mops(fn, np.ascontiguousarray(inputs64[fn][0][:1 << 20]), quad=False)
+        context[fn] = {"quadmath_mops": q, "libm_mops": c,
+                       "twofold_over_quadmath": per_core[fn]["mops"] / q}
     return {"value": passes * 4 * n / t / 1e9, "unit": "Gelem/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d whole pass(es) over the step's 4 binary64 arrays of %d elements, "
                       "scalar oracle, OpenMP static schedule" % (passes, n),
             "seconds": t, "host_cpus": os.cpu_count(),
-            "one_thread": {"sample": core_sample, "per_function": per_core}}
+            "one_thread": {"sample": core_sample, "per_function": per_core},
+            "context_one_thread": context}
 
 
 def bench_small(tf, workloads, reps=200):

@@ -29,6 +29,11 @@
  *           2: such a result that fails that bar
  *           3: not measured: x0 + x1 not finite, outside the function's domain,
  *              f beyond the format's largest finite value, or z0 not finite
+ * qref_quad(fn, x, out, n) and qref_libm(fn, x, out, n) call one libquadmath
+ * function (expq, expm1q, logq, log1pq) or one C library function (exp, expm1,
+ * log, log1p) per element, for the benchmark's context timing of the paper's
+ * comparison of twofold functions with quad precision (section "Analysis >
+ * Performance").
  * qref_eval(fn, x0, x1, out, ex, n) returns f(x0 + x1) (binary64 x0, x1) as
  * (out[3i] + out[3i+1] + out[3i+2])*2^ex[i], the quad significand m = f*2^-ex
  * in [1/2, 1) cut into three doubles (exactly: 113 bits fit in three), for
@@ -107,6 +112,33 @@ void qref_check(int fn, int fmt, const void* x0, const void* x1, const void* z0,
         const float *c = (const float*)z0, *d = (const float*)z1;
 #pragma omp parallel for schedule(dynamic, 4096) num_threads(threads)
         for (i = 0; i < m; i++) one(fn, 1, a[i], b[i], c[i], d[i], l0, rel + i, cls + i);
+    }
+}
+
+void qref_quad(int fn, const double* x, double* out, size_t n)
+{
+    for (size_t i = 0; i < n; i++) {
+        q v = x[i], r;
+        switch (fn) {
+        case 0: r = expq(v); break;
+        case 1: r = expm1q(v); break;
+        case 2: r = logq(v); break;
+        default: r = log1pq(v); break;
+        }
+        out[i] = (double)r;
+    }
+}
+
+void qref_libm(int fn, const double* x, double* out, size_t n)
+{
+    for (size_t i = 0; i < n; i++) {
+        double v = x[i];
+        switch (fn) {
+        case 0: out[i] = exp(v); break;
+        case 1: out[i] = expm1(v); break;
+        case 2: out[i] = log(v); break;
+        default: out[i] = log1p(v); break;
+        }
     }
 }
 

@@ -41,6 +41,8 @@ def _load():
         P, S, I, D = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
         lib.qref_check.argtypes = [I, I, P, P, P, P, S, D, P, P, I]
         lib.qref_eval.argtypes = [I, P, P, P, P, S]
+        lib.qref_quad.argtypes = [I, P, P, S]
+        lib.qref_libm.argtypes = [I, P, P, S]
         _lib.append(lib)
     return _lib[0]
 
@@ -75,3 +77,18 @@ def evaluate(fn, x0, x1):
     ex = np.empty(x0.size, np.int32)
     _load().qref_eval(FN[fn], _p(x0), _p(x1), _p(parts), _p(ex), x0.size)
     return parts, ex
+
+
+def context_mops(fn, x, quad=True):
+    """Millions of calls per second of one libquadmath function (quad=True:
+    expq, expm1q, logq, log1pq) or one C library function (exp, ...) of
+    binary64 arguments, on one thread: the comparison systems the paper times
+    its twofold functions against (section "Analysis > Performance")."""
+    import time
+    x = np.ascontiguousarray(x, np.float64)
+    out = np.empty_like(x)
+    f = _load().qref_quad if quad else _load().qref_libm
+    f(FN[fn], _p(x), _p(out), min(x.size, 1024))          # warm
+    t0 = time.perf_counter()
+    f(FN[fn], _p(x), _p(out), x.size)
+    return x.size / (time.perf_counter() - t0) / 1e6
