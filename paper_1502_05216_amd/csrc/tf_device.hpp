@@ -696,46 +696,83 @@ __device__ __forceinline__ void tlog_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt
     }
 }
 
+// tlog1p on a fast wave (tlog1p_fast_arg on every lane), in parts, so that a
+// kernel can evaluate the Newton seeds log1p_1x(a0 + a1) of a wave's elements
+// together.  The head renormalises y into v and, on outer lanes
+// (v0 < -1/2 or v0 > 1), reduces 1 + v to 2^nn z with a = z - 1; elsewhere
+// a = v.  The main part x0 = log1p(y0) is computed apart.  The tail takes x0
+// and the seed and finishes the Newton step.
+//
+// Outer lanes of a fast wave have v0 > 1 or -1 <= v0 < -1/2 (then 1 + v0 is
+// exact), with |v1| <= ulp(v0)/2: both sums of the reduction are fast
+// two-sums with the exact errors of the general form.
+template <class T> struct Tlog1pHead {
+    Tw<T> a;    // the Newton argument: |a0 + a1| <= 1
+    int nn;     // outer lanes: 1 + y = 2^nn (1 + a); 0 elsewhere
+};
+template <class T>
+__device__ __forceinline__ Tlog1pHead<T> tlog1p_fast_head(T y0, T y1, bool& any_outer) {
+    Tlog1pHead<T> h;
+    Tw<T> v = fast_two_sum_pz(y0, y1);
+    const bool outer = v.x0 < T(-0.5) || v.x0 > T(1);
+    h.a = v;
+    h.nn = 0;
+    any_outer = __any(outer);
+    if (any_outer) {                                  // log of the renormalised 1 + y
+        Tw<T> st = fast_two_sum(v.x0, T(1));
+        Tw<T> w = fast_two_sum(st.x0, st.x1 + v.x1);
+        int nn;
+        Tw<T> z = log_scale(w, nn);
+        h.nn = outer ? nn : 0;
+        h.a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
+    }
+    return h;
+}
+// The seed's argument; |a0 + a1| <= 1, so the seed is log1p_1x<true, true>.
+template <class T> __device__ __forceinline__ T tlog1p_seed_arg(const Tlog1pHead<T>& h) {
+    return h.a.x0 + h.a.x1;
+}
+template <class T>
+__device__ __forceinline__ T tlog1p_fast_tail(const Tlog1pHead<T>& h, T x0, T seed,
+                                              bool any_outer, Pm1Tab<T> mt) {
+    Tw<T> X = newton_seeded<true>(h.a, seed, mt);
+    // + 0 ln2 returns X itself up to the sign of a zero second part, which
+    // the final sum below does not keep: no select needed
+    if (any_outer) X = add_n_ln2<true>(X, h.nn);
+    return X.x1 + (X.x0 - x0);
+}
+
 // tlog1p.  FAST: tlog1p_fast_arg (y0 and y0 + y1 above -1 and finite,
 // |y1| <= |y0|).
 template <bool FAST, class T>
 __device__ __forceinline__ void tlog1p_elem(T y0, T y1, LogTab<T> lt, Pm1Tab<T> mt, T& x0o,
                                             T& x1o) {
     using K = P<T>;
-    T x0 = log1p_1x<FAST>(y0, lt);
-    Tw<T> v = FAST ? fast_two_sum_pz(y0, y1) : two_sum(y0, y1);
-    bool outer = v.x0 < T(-0.5) || v.x0 > T(1);
-    Tw<T> a = v;
-    Tw<T> w = v;
-    int nn = 0;
-    const bool any_outer = __any(outer);
-    if (any_outer) {                                  // log of the renormalised 1 + y
-        if constexpr (FAST) {
-            // Outer lanes of a fast wave have v0 > 1 or -1 <= v0 < -1/2 (then
-            // 1 + v0 is exact), with |v1| <= ulp(v0)/2: both sums below are
-            // fast two-sums with the exact errors of the general form.
-            Tw<T> st = fast_two_sum(v.x0, T(1));
-            w = fast_two_sum(st.x0, st.x1 + v.x1);
-        } else {
+    if constexpr (FAST) {
+        const T x0 = log1p_1x<true>(y0, lt);
+        bool any_outer;
+        Tlog1pHead<T> h = tlog1p_fast_head(y0, y1, any_outer);
+        T seed = log1p_1x<true, true>(tlog1p_seed_arg(h), lt);
+        x0o = x0;
+        x1o = tlog1p_fast_tail(h, x0, seed, any_outer, mt);
+    } else {
+        T x0 = log1p_1x<false>(y0, lt);
+        Tw<T> v = two_sum(y0, y1);
+        bool outer = v.x0 < T(-0.5) || v.x0 > T(1);
+        Tw<T> a = v;
+        Tw<T> w = v;
+        int nn = 0;
+        const bool any_outer = __any(outer);
+        if (any_outer) {                              // log of the renormalised 1 + y
             w = add_td(v, T(1));
             w = two_sum(w.x0, w.x1);
+            Tw<T> z = log_scale(w, nn);
+            a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
         }
-        Tw<T> z = log_scale(w, nn);
-        a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, v);
-    }
-    Tw<T> X = plog_newton<FAST>(a, lt, mt);
-    if constexpr (FAST) {
-        // + 0 ln2 returns X itself up to the sign of a zero second part, which
-        // the final sum below does not keep: no select needed
-        if (any_outer) X = add_n_ln2<FAST>(X, outer ? nn : 0);
-    } else {
-        if (any_outer) X = sel(outer, add_n_ln2<FAST>(X, outer ? nn : 0), X);
-    }
-    T x1 = X.x1 + (X.x0 - x0);
-    x0o = x0;
-    if constexpr (FAST) {
-        x1o = x1;
-    } else {
+        Tw<T> X = plog_newton<false>(a, lt, mt);
+        if (any_outer) X = sel(outer, add_n_ln2<false>(X, outer ? nn : 0), X);
+        T x1 = X.x1 + (X.x0 - x0);
+        x0o = x0;
         x1 = (outer && any_outer) ? log_domain_x1(w.x0, x1) : x1;
         x1 = (v.x0 == K::INF) ? K::INF : x1;
         x1 = isnan_(v.x0) ? K::qnan() : x1;

@@ -11,7 +11,8 @@
 // handling.  The rare branch of texpm1 (|x0| > ln 2: pexp0(x0) - 1) does not
 // hold the fast body back: such lanes go to a per-wave LDS queue that is
 // drained with full waves.  tlog1p's outer branch (the log of 1 + y) runs
-// under a wave vote inside the fast body.
+// under a wave vote inside the fast body, and its fast waves evaluate only the
+// Newton seeds that differ from the main part, packed 64 to a pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,12 +71,94 @@ __device__ __forceinline__ void eval_general(const L& lds, T a, T b, bool x1_tin
     else tlog1p_elem<false>(a, b, lds.lt(), lds.mt(), r0, r1);
 }
 
+// Per-wave LDS slots of tlog1p's Newton seeds (up to 4 per lane: 256 binary64
+// values per wave, reused as binary32).
+constexpr int kSeedSlots = 256;
+struct SeedSlots {
+    double v[kBlock / 64][kSeedSlots];
+};
+template <class T> __device__ __forceinline__ T* seed_slots(SeedSlots& ss) {
+    return reinterpret_cast<T*>(ss.v[threadIdx.x / 64]);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A fast tlog1p wave's 64 x EPT elements.  The Newton seed of an element is
+// log1p_1x(a0 + a1).  Where that argument equals y0 bit for bit (an inner
+// lane whose y is already renormalised, v0 = y0), the seed is the element's
+// main part x0: both are the 1x log1p of the same value in [-1/2, 1], where
+// its steps do not depend on the SMALL premise.  The other seed arguments (y1
+// beyond half an ulp of y0, and the outer lanes) are packed into the wave's
+// LDS slots by a ballot prefix count and evaluated one per lane, so the wave
+// runs one 1x log1p per 64 such elements instead of one per element slot.
+// The main parts are computed while the packed arguments and the seeds are in
+// flight through LDS.  Every lane of the wave is active (fast waves only).
+template <class T, int EPT>
+__device__ __forceinline__ void tlog1p_fast_tile(const Vec<T, EPT>& y0, const Vec<T, EPT>& y1,
+                                                 Vec<T, EPT>& r0, Vec<T, EPT>& r1, T* slot,
+                                                 LogTab<T> lt, Pm1Tab<T> mt) {
+    static_assert(64 * EPT <= kSeedSlots, "seed slots");
+    const int lane = threadIdx.x & 63;
+    Tlog1pHead<T> h[EPT];
+    bool any_outer[EPT];
+    T arg[EPT];
+    bool need[EPT];
+    int rank[EPT];
+    int total = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        h[e] = tlog1p_fast_head(y0.v[e], y1.v[e], any_outer[e]);
+        arg[e] = tlog1p_seed_arg(h[e]);
+        need[e] = P<T>::bits(arg[e]) != P<T>::bits(y0.v[e]);
+        const unsigned long long m = __ballot(need[e]);
+        rank[e] = total + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        total += __popcll(m);
+        if (need[e]) slot[rank[e]] = arg[e];
+    }
+    wave_sync();
+    // first pass: lanes 0..63 take the first 64 packed arguments; the main
+    // parts of the first half of the elements run beside it, in the same
+    // basic block, so they cover the LDS latencies
+    constexpr int H = (EPT + 1) / 2;
+    T x0[EPT];
+    T u = slot[lane];
+    u = lane < total ? u : T(0);
+#pragma unroll
+    for (int e = 0; e < H; ++e) x0[e] = log1p_1x<true>(y0.v[e], lt);
+    slot[lane] = log1p_1x<true, true>(u, lt);
+#pragma unroll
+    for (int p = 1; p < EPT; ++p) {
+        if (64 * p < total) {                         // wave-uniform
+            T w = slot[64 * p + lane];
+            w = 64 * p + lane < total ? w : T(0);
+            slot[64 * p + lane] = log1p_1x<true, true>(w, lt);
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int e = H; e < EPT; ++e) x0[e] = log1p_1x<true>(y0.v[e], lt);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const T packed = slot[need[e] ? rank[e] : 0];   // unconditional LDS read
+        const T seed = need[e] ? packed : x0[e];
+        r0.v[e] = x0[e];
+        r1.v[e] = tlog1p_fast_tail(h[e], x0[e], seed, any_outer[e], mt);
+    }
+    wave_sync();
+}
+
 // Evaluates a thread's EPT elements.  Returns true when the wave took the fast
 // form; for texpm1 the fast form leaves the |x0| > ln 2 lanes to the caller
 // (bit e of *deferred set for such an element).
 template <class T, int FN, int EPT, class L>
 __device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, const Vec<T, EPT>& b,
-                                          Vec<T, EPT>& r0, Vec<T, EPT>& r1, unsigned* deferred) {
+                                          Vec<T, EPT>& r0, Vec<T, EPT>& r1, unsigned* deferred,
+                                          T* slot) {
     bool fast = true, tiny = true;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -84,6 +167,10 @@ __device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, co
     }
     *deferred = 0;
     if (__all(fast)) {
+        if constexpr (FN == FN_TLOG1P) {
+            tlog1p_fast_tile<T, EPT>(a, b, r0, r1, slot, lds.lt(), lds.mt());
+            return true;
+        }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if constexpr (FN == FN_TEXP) {
@@ -91,10 +178,8 @@ __device__ __forceinline__ bool eval_tile(const L& lds, const Vec<T, EPT>& a, co
             } else if constexpr (FN == FN_TEXPM1) {
                 if (texpm1_small_fast(a.v[e], b.v[e], lds.et(), lds.mt(), r0.v[e], r1.v[e]))
                     *deferred |= 1u << e;
-            } else if constexpr (FN == FN_TLOG) {
-                tlog_elem<true>(a.v[e], b.v[e], lds.lt(), lds.mt(), r0.v[e], r1.v[e]);
             } else {
-                tlog1p_elem<true>(a.v[e], b.v[e], lds.lt(), lds.mt(), r0.v[e], r1.v[e]);
+                tlog_elem<true>(a.v[e], b.v[e], lds.lt(), lds.mt(), r0.v[e], r1.v[e]);
             }
         }
         return true;
@@ -210,7 +295,7 @@ template <int FN> constexpr bool kPeel = FN == FN_TEXPM1 || FN == FN_TLOG;
 // current tile is evaluated), so HBM latency overlaps arithmetic.  Deferred
 // texpm1 lanes go to the wave queue, which the caller drains at the end.
 template <class T, int FN, int EPT, int PD, class L>
-__device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const T* x0,
+__device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, T* slot, const T* x0,
                                           const T* x1, T* z0, T* z1, size_t t0, size_t t_end,
                                           size_t step) {
     constexpr bool QUEUE = kDefers<FN>;
@@ -250,7 +335,7 @@ __device__ __forceinline__ void run_tiles(const L& lds, WaveQueue<T>& wq, const 
             vload<NT>(b[PD], x1 + tn * TILE + off);
         }
         unsigned deferred;
-        eval_tile<T, FN, EPT>(lds, a[0], b[0], r0, r1, &deferred);
+        eval_tile<T, FN, EPT>(lds, a[0], b[0], r0, r1, &deferred, slot);
         const size_t base = t * TILE + off;
         vstore<NT>(z0 + base, r0);
         // Every lane stores z1, so each store covers whole lines; a deferred
@@ -328,12 +413,14 @@ __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T*
                                                     size_t n) {
     __shared__ typename LdsFor<T, FN>::type lds;
     __shared__ QueueSlots qs;
+    __shared__ SeedSlots ss;
     lds.load();
     __syncthreads();
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t nfull = n / TILE;
     WaveQueue<T> wq = wave_queue<T>(qs);
-    run_tiles<T, FN, EPT, PD>(lds, wq, x0, x1, z0, z1, blockIdx.x, nfull, gridDim.x);
+    run_tiles<T, FN, EPT, PD>(lds, wq, seed_slots<T>(ss), x0, x1, z0, z1, blockIdx.x, nfull,
+                              gridDim.x);
     if constexpr (kDefers<FN>) {
         while (wq.n > 0) drain_deferred<T, FN>(lds, wq, threadIdx.x & 63);
     }
@@ -383,8 +470,9 @@ __device__ __forceinline__ void batch_stage(BatchLds& lds, int key) {
 }
 
 template <class T, int FN, int EPT, class L>
-__device__ __forceinline__ void batch_chunk(const L& lds, WaveQueue<T>& wq, const BatchDesc& d,
-                                            unsigned chunk, unsigned chunk_tiles) {
+__device__ __forceinline__ void batch_chunk(const L& lds, WaveQueue<T>& wq, T* slot,
+                                            const BatchDesc& d, unsigned chunk,
+                                            unsigned chunk_tiles) {
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t start = (size_t)chunk * chunk_tiles * TILE;
     const size_t lim = start + (size_t)chunk_tiles * TILE;
@@ -396,7 +484,7 @@ __device__ __forceinline__ void batch_chunk(const L& lds, WaveQueue<T>& wq, cons
     size_t g0 = start;
     if (d.aligned) {
         const size_t t0 = start / TILE, t1 = end / TILE;
-        run_tiles<T, FN, EPT, 1>(lds, wq, x0, x1, z0, z1, t0, t1, 1);
+        run_tiles<T, FN, EPT, 1>(lds, wq, slot, x0, x1, z0, z1, t0, t1, 1);
         g0 = t1 * TILE;
     }
     if (g0 < end) run_guarded<T, FN, EPT>(lds, x0, x1, z0, z1, g0, end);
@@ -404,17 +492,20 @@ __device__ __forceinline__ void batch_chunk(const L& lds, WaveQueue<T>& wq, cons
 
 template <int EPT64, int EPT32>
 __device__ __forceinline__ void batch_dispatch(BatchLds& lds, WaveQueue<double>& q64,
-                                               WaveQueue<float>& q32, const BatchDesc& d,
-                                               int key, unsigned chunk, unsigned ct) {
+                                               WaveQueue<float>& q32, SeedSlots& ss,
+                                               const BatchDesc& d, int key, unsigned chunk,
+                                               unsigned ct) {
+    double* s64 = seed_slots<double>(ss);
+    float* s32 = seed_slots<float>(ss);
     switch (key) {
-        case 0: batch_chunk<double, FN_TEXP, EPT64>(lds.d_exp, q64, d, chunk, ct); break;
-        case 2: batch_chunk<double, FN_TEXPM1, EPT64>(lds.d_expm1, q64, d, chunk, ct); break;
-        case 4: batch_chunk<double, FN_TLOG, EPT64>(lds.d_log, q64, d, chunk, ct); break;
-        case 6: batch_chunk<double, FN_TLOG1P, EPT64>(lds.d_log, q64, d, chunk, ct); break;
-        case 1: batch_chunk<float, FN_TEXP, EPT32>(lds.f_exp, q32, d, chunk, ct); break;
-        case 3: batch_chunk<float, FN_TEXPM1, EPT32>(lds.f_expm1, q32, d, chunk, ct); break;
-        case 5: batch_chunk<float, FN_TLOG, EPT32>(lds.f_log, q32, d, chunk, ct); break;
-        default: batch_chunk<float, FN_TLOG1P, EPT32>(lds.f_log, q32, d, chunk, ct); break;
+        case 0: batch_chunk<double, FN_TEXP, EPT64>(lds.d_exp, q64, s64, d, chunk, ct); break;
+        case 2: batch_chunk<double, FN_TEXPM1, EPT64>(lds.d_expm1, q64, s64, d, chunk, ct); break;
+        case 4: batch_chunk<double, FN_TLOG, EPT64>(lds.d_log, q64, s64, d, chunk, ct); break;
+        case 6: batch_chunk<double, FN_TLOG1P, EPT64>(lds.d_log, q64, s64, d, chunk, ct); break;
+        case 1: batch_chunk<float, FN_TEXP, EPT32>(lds.f_exp, q32, s32, d, chunk, ct); break;
+        case 3: batch_chunk<float, FN_TEXPM1, EPT32>(lds.f_expm1, q32, s32, d, chunk, ct); break;
+        case 5: batch_chunk<float, FN_TLOG, EPT32>(lds.f_log, q32, s32, d, chunk, ct); break;
+        default: batch_chunk<float, FN_TLOG1P, EPT32>(lds.f_log, q32, s32, d, chunk, ct); break;
     }
 }
 
@@ -445,6 +536,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TF_BATCH
                                                   unsigned* counter, unsigned chunk_tiles) {
     __shared__ BatchLds lds;
     __shared__ QueueSlots qs;
+    __shared__ SeedSlots ss;
     __shared__ unsigned s_chunk;
     WaveQueue<double> q64 = wave_queue<double>(qs);
     WaveQueue<float> q32 = wave_queue<float>(qs);
@@ -466,7 +558,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TF_BATCH
             __syncthreads();
             cur = key;
         }
-        batch_dispatch<EPT64, EPT32>(lds, q64, q32, d, key, ch.chunk, chunk_tiles);
+        batch_dispatch<EPT64, EPT32>(lds, q64, q32, ss, d, key, ch.chunk, chunk_tiles);
     }
     if (cur >= 0) batch_drain(lds, q64, q32, cur);
 }

@@ -117,7 +117,9 @@ def trace(args):
              "median | min | max | mean of selected |", "|---|---|---|---|---|---|---|---|---|---|---|"]
     for (name, grid, block), g in sorted(groups.items(), key=lambda t: t[1]["first"]):
         d = [t for _, t in sorted(g["d"])]
-        if len(d) < args.min_dispatches or sum(d) / len(d) < args.min_mean:
+        if len(d) < args.min_dispatches:
+            continue
+        if sum(d) / len(d) < args.min_mean and len(d) < args.keep_dispatches:
             continue
         ds = sorted(d)
         sel = ""
@@ -268,6 +270,8 @@ def main():
     s.add_argument("--min-dispatches", type=int, default=2)
     s.add_argument("--min-mean", type=float, default=0.0, help="drop groups with a smaller "
                    "mean duration (us), e.g. the small per-array launches")
+    s.add_argument("--keep-dispatches", type=int, default=1 << 30,
+                   help="keep groups with at least this many dispatches whatever their mean")
     s.add_argument("--note", default="")
     s.add_argument("--out", required=True)
     t = sub.add_parser("traffic")

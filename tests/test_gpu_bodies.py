@@ -174,3 +174,45 @@ def test_fast_body_at_branch_points(tf, fn, dt, ept):
         ok = same_bits(a[keep], b[keep])
         assert ok.all(), "%s %s: %s fast and general bodies differ at %d elements" % (
             fn, dts, name, (~ok).sum())
+
+
+@pytest.mark.parametrize("mix", ["none", "quarter", "half", "all"])
+@pytest.mark.parametrize("ept", [1, 2, 4])
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+def test_tlog1p_shared_seeds(tf, dt, ept, mix):
+    """tlog1p's fast waves take the Newton seed of an element from its main
+    part when the seed's argument equals y0, and evaluate the other seeds
+    packed 64 to a pass.  Waves where no element, a quarter, half or every
+    element needs its own seed (y1 beyond half an ulp of y0, or the outer
+    branch), at 1, 2 and 4 elements per thread (up to four passes): the fast
+    body against the general body bit for bit, and against the oracle."""
+    import oracle
+    from paper_1502_05216_amd import _lib
+    from parity_util import compare
+    dts = "f64" if dt == np.float64 else "f32"
+    _, bpc, pd = _lib.get_launch_config("tlog1p", dts)
+    _lib.set_launch_config("tlog1p", dts, ept, bpc, pd)
+    n = 256 * 4 * 20
+    rng = np.random.default_rng(96 + ept)
+    p = {"none": 0.0, "quarter": 0.25, "half": 0.5, "all": 1.0}[mix]
+    need = rng.random(n) < p
+    x0 = rng.uniform(-0.5, 1.0, n).astype(dt)                    # inner, seed shared
+    x1 = (x0 * rng.uniform(-1, 1, n).astype(dt) * dt(np.finfo(dt).eps / 4)).astype(dt)
+    outer = need & (rng.random(n) < 0.5)
+    x0[outer] = rng.uniform(1.0, 300.0, outer.sum()).astype(dt)   # outer branch
+    x1[outer] = (x0[outer] * dt(np.finfo(dt).eps / 4)).astype(dt)
+    loose = need & ~outer                                         # inner, y1 > ulp(y0)/2
+    x1[loose] = (np.spacing(np.abs(x0[loose])) * dt(0.75)).astype(dt)
+    print("case tlog1p shared seeds", dts, "ept", ept, mix, flush=True)
+    a0, a1 = gpu_call(tf, "tlog1p", x0, x1)
+    o0, o1 = getattr(oracle, "tlog1p" + ("" if dt == np.float64 else "f"))(x0, x1)
+    compare(a0, a1, o0, o1, "tlog1p %s shared seeds ept %d %s" % (dts, ept, mix))
+    p1 = x1.copy()
+    p1[::64] = np.nan
+    b0, b1 = gpu_call(tf, "tlog1p", x0, p1)
+    keep = np.ones(n, bool)
+    keep[::64] = False
+    for name, a, b in (("z0", a0, b0), ("z1", a1, b1)):
+        ok = same_bits(a[keep], b[keep])
+        assert ok.all(), "tlog1p %s ept %d %s: %s fast and general bodies differ at %d" % (
+            dts, ept, mix, name, (~ok).sum())
