@@ -161,6 +161,81 @@ __device__ __forceinline__ void vstore(T* p, const Vec<T, EPT>& r) {
     }
 }
 
+// Per-wave LDS slots of the packed Newton seeds of the log1p kernels (up to 4
+// per lane: 256 binary64 values per wave, reused as binary32).
+constexpr int kSeedSlots = 256;
+struct SeedSlots {
+    double v[kBlock / 64][kSeedSlots];
+};
+template <class T> __device__ __forceinline__ T* seed_slots(SeedSlots& ss) {
+    return reinterpret_cast<T*>(ss.v[threadIdx.x / 64]);
+}
+
+// Orders this wave's LDS accesses before and after it (compiler and memory).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The Newton seeds log1p_1x(arg) of the 64 x EPT elements of a fast wave of a
+// log1p kernel (every lane active), together with their main parts
+// x0 = log1p_1x(y0), which main(e) computes.  Where arg equals y0 bit for bit
+// (an inner lane whose argument is already coupled) the seed is x0: both are
+// the 1x log1p of the same value in [-1/2, 1], where its steps do not depend
+// on the SMALL premise.  The other arguments (|arg| <= 1) are packed into the
+// wave's LDS slots by a ballot prefix count and evaluated one per lane, so the
+// wave runs one 1x log1p per 64 such elements instead of one per element
+// slot.  The main parts are computed between the LDS writes and reads, in the
+// same basic block, so that they cover the LDS latency.
+template <class T, int EPT, class Main>
+__device__ __forceinline__ void wave_log1p_seeds(const T (&arg)[EPT], const T (&y0)[EPT],
+                                                 T (&x0)[EPT], T (&seed)[EPT], T* slot,
+                                                 LogTab<T> lt, Main&& main) {
+    static_assert(64 * EPT <= kSeedSlots, "seed slots");
+    const int lane = threadIdx.x & 63;
+    bool need[EPT];
+    int rank[EPT];
+    int total = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        need[e] = P<T>::bits(arg[e]) != P<T>::bits(y0[e]);
+        const unsigned long long m = __ballot(need[e]);
+        rank[e] = total + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        total += __popcll(m);
+        if (need[e]) slot[rank[e]] = arg[e];
+    }
+    wave_sync();
+    // first pass: lanes 0..63 take the first 64 packed arguments, beside the
+    // main parts of the first half of the elements
+    constexpr int H = (EPT + 1) / 2;
+    T u = slot[lane];
+    u = lane < total ? u : T(0);
+#pragma unroll
+    for (int e = 0; e < H; ++e) x0[e] = main(e);
+    slot[lane] = log1p_1x<true, true>(u, lt);
+#pragma unroll
+    for (int p = 1; p < EPT; ++p) {
+        if (64 * p < total) {                         // wave-uniform
+            T w = slot[64 * p + lane];
+            w = 64 * p + lane < total ? w : T(0);
+            slot[64 * p + lane] = log1p_1x<true, true>(w, lt);
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int e = H; e < EPT; ++e) x0[e] = main(e);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        // an unconditional LDS read, then a select of the value (a select of
+        // the two sources would put x0 on the stack)
+        const T packed = slot[need[e] ? rank[e] : 0];
+        seed[e] = need[e] ? packed : x0[e];
+    }
+    wave_sync();
+}
+
 // ----------------------------------------------------------------------------
 // Host side
 // ----------------------------------------------------------------------------

@@ -961,35 +961,65 @@ __device__ __forceinline__ Tw<T> plog_coupled_core(Tw<T> y, LogTab<T> lt, Pm1Tab
 // plog1p0 core (dotted y0 in (-1, inf), not renormalised): outside [-1/2, 1]
 // the plog of the renormalised 1 + y0, inside the Newton correction with
 // a = y0 seeded with log1p(y0).  One Newton step per lane: the branch only
-// selects its argument and seed.
+// selects its argument and seed.  In two halves around the seed (head, seed
+// argument, tail), so that a kernel can evaluate the seeds of a wave together;
+// plog1p of a coupled argument (plog1p_head, plog1p_tail) likewise.
+template <class T> struct Log1pCoreHead {
+    Tw<T> a;     // the Newton argument
+    int n;       // outer lanes: 1 + y = 2^n (1 + a)
+    bool outer;  // y0 < -1/2 or y0 > 1
+};
+template <class T> __device__ __forceinline__ Log1pCoreHead<T> plog1p0_head(T y0) {
+    Log1pCoreHead<T> h;
+    h.outer = y0 < T(-0.5) || y0 > T(1);
+    Tw<T> z = log_scale(two_sum(T(1), y0), h.n);
+    h.a = sel(h.outer, Tw<T>{z.x0 - T(1), z.x1}, Tw<T>{y0, T(0)});
+    return h;
+}
+template <class T>
+__device__ __forceinline__ T plog1p0_seed_arg(const Log1pCoreHead<T>& h, T y0) {
+    return h.outer ? h.a.x0 + h.a.x1 : y0;
+}
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog1p0_tail(const Log1pCoreHead<T>& h, T r0, Pm1Tab<T> mt) {
+    Tw<T> X = newton_seeded<FAST>(h.a, r0, mt);
+    return sel(h.outer, add_n_ln2<FAST>(X, h.outer ? h.n : 0), X);
+}
 template <bool FAST, class T>
 __device__ __forceinline__ Tw<T> plog1p0_core(T y0, LogTab<T> lt, Pm1Tab<T> mt) {
-    const bool outer = y0 < T(-0.5) || y0 > T(1);
-    int n;
-    Tw<T> z = log_scale(two_sum(T(1), y0), n);
-    Tw<T> a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, Tw<T>{y0, T(0)});
-    T r0 = log1p_1x<FAST, FAST>(outer ? a.x0 + a.x1 : y0, lt);
-    Tw<T> X = newton_seeded<FAST>(a, r0, mt);
-    return sel(outer, add_n_ln2<FAST>(X, outer ? n : 0), X);
+    Log1pCoreHead<T> h = plog1p0_head(y0);
+    return plog1p0_tail<FAST>(h, log1p_1x<FAST, FAST>(plog1p0_seed_arg(h, y0), lt), mt);
 }
 
 // plog1p core (coupled y, y0 in (-1, inf), not renormalised): outside
 // [-1/2, 1] the plog of the renormalised 1 + y, inside the Newton step on
 // a = y seeded with log1p(y0 + y1).
-template <bool FAST, class T>
-__device__ __forceinline__ Tw<T> plog1p_core(Tw<T> y, LogTab<T> lt, Pm1Tab<T> mt) {
-    const bool outer = y.x0 < T(-0.5) || y.x0 > T(1);
-    Tw<T> a = y;
-    int n = 0;
-    const bool any_outer = __any(outer);
+template <class T>
+__device__ __forceinline__ Log1pCoreHead<T> plog1p_head(Tw<T> y, bool& any_outer) {
+    Log1pCoreHead<T> h;
+    h.outer = y.x0 < T(-0.5) || y.x0 > T(1);
+    h.a = y;
+    h.n = 0;
+    any_outer = __any(h.outer);
     if (any_outer) {
         Tw<T> w = add_td(y, T(1));
-        Tw<T> z = log_scale(two_sum(w.x0, w.x1), n);
-        a = sel(outer, Tw<T>{z.x0 - T(1), z.x1}, y);
+        Tw<T> z = log_scale(two_sum(w.x0, w.x1), h.n);
+        h.a = sel(h.outer, Tw<T>{z.x0 - T(1), z.x1}, y);
     }
-    Tw<T> X = plog_newton<FAST>(a, lt, mt);
-    if (any_outer) X = sel(outer, add_n_ln2<FAST>(X, outer ? n : 0), X);
+    return h;
+}
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog1p_tail(const Log1pCoreHead<T>& h, T r0, bool any_outer,
+                                             Pm1Tab<T> mt) {
+    Tw<T> X = newton_seeded<FAST>(h.a, r0, mt);
+    if (any_outer) X = sel(h.outer, add_n_ln2<FAST>(X, h.outer ? h.n : 0), X);
     return X;
+}
+template <bool FAST, class T>
+__device__ __forceinline__ Tw<T> plog1p_core(Tw<T> y, LogTab<T> lt, Pm1Tab<T> mt) {
+    bool any_outer;
+    Log1pCoreHead<T> h = plog1p_head(y, any_outer);
+    return plog1p_tail<FAST>(h, log1p_1x<FAST, FAST>(h.a.x0 + h.a.x1, lt), any_outer, mt);
 }
 
 // The four log-family functions of each kind.  P: p-function (renormalised

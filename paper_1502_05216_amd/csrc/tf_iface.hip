@@ -11,7 +11,8 @@
 // for a coupled argument) and run their kernels.  The others stream x0 (and
 // x1) -> z0, z1 once, with the element functions of tf_device.hpp: a wave
 // whose lanes all hold an ordinary argument takes the FAST form, any other
-// wave the general form.  There is no deferred-lane queue here: on the waves
+// wave the general form (tlog1p0 and tlog1pp share their Newton seeds with the
+// main parts on fast waves, as tlog1p does).  There is no deferred-lane queue here: on the waves
 // of pexpm10 / texpm10 / pexpm1 that hold a lane with |x0| > ln 2 every lane
 // runs pexp0 - 1 as well.
 #include <hip/hip_runtime.h>
@@ -104,9 +105,45 @@ __device__ __forceinline__ void eval_iface(const L& lds, T a, T b, bool x1_tiny,
     }
 }
 
+// tlog1p0 and tlog1pp on a fast wave: the heads, the Newton seeds shared with
+// the main parts log1p(y0) (every inner lane of tlog1p0, and of tlog1pp where
+// the argument is coupled) or packed (wave_log1p_seeds), the tails.  The same
+// values as log_iface_elem, bit for bit.
+template <class T, int VF, int EPT, class L>
+__device__ __forceinline__ void log1p_iface_fast_tile(const L& lds, const Vec<T, EPT>& a,
+                                                      const Vec<T, EPT>& b, Vec<T, EPT>& r0,
+                                                      Vec<T, EPT>& r1, T* slot) {
+    Log1pCoreHead<T> h[EPT];
+    bool any_outer[EPT];
+    T arg[EPT], y[EPT], x0[EPT], seed[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        if constexpr (VF == V_TLOG1P0) {
+            h[e] = plog1p0_head(a.v[e]);
+            arg[e] = plog1p0_seed_arg(h[e], a.v[e]);
+            any_outer[e] = true;
+        } else {
+            h[e] = plog1p_head(Tw<T>{a.v[e], b.v[e]}, any_outer[e]);
+            arg[e] = h[e].a.x0 + h[e].a.x1;
+        }
+        y[e] = a.v[e];
+    }
+    const LogTab<T> lt = lds.lt();
+    wave_log1p_seeds<T, EPT>(arg, y, x0, seed, slot, lt,
+                             [&](int e) { return log1p_1x<true>(a.v[e], lt); });
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        Tw<T> X;
+        if constexpr (VF == V_TLOG1P0) X = plog1p0_tail<true>(h[e], seed[e], lds.mt());
+        else X = plog1p_tail<true>(h[e], seed[e], any_outer[e], lds.mt());
+        r0.v[e] = x0[e];
+        r1.v[e] = X.x1 + (X.x0 - x0[e]);
+    }
+}
+
 template <class T, int VF, int EPT, class L>
 __device__ __forceinline__ void iface_tile(const L& lds, const Vec<T, EPT>& a, const Vec<T, EPT>& b,
-                                           Vec<T, EPT>& r0, Vec<T, EPT>& r1) {
+                                           Vec<T, EPT>& r0, Vec<T, EPT>& r1, T* slot) {
     bool fast = true, tiny = true;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -114,6 +151,10 @@ __device__ __forceinline__ void iface_tile(const L& lds, const Vec<T, EPT>& a, c
         tiny = tiny && (fabs_(b.v[e]) < P<T>::EXPM1_TINY);
     }
     if (__all(fast)) {
+        if constexpr (VF == V_TLOG1P0 || VF == V_TLOG1PP) {
+            log1p_iface_fast_tile<T, VF, EPT>(lds, a, b, r0, r1, slot);
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
             eval_iface<T, VF, true>(lds, a.v[e], b.v[e], true, r0.v[e], r1.v[e]);
@@ -132,8 +173,10 @@ __global__ __launch_bounds__(kBlock) void k_iface(const T* x0, const T* x1, T* z
     constexpr bool DOT = VfInfo<VF>::DOTTED;
     constexpr bool NT = compute_nt<T, VfInfo<VF>::EXP1>();
     __shared__ typename VfLds<T, VF>::type lds;
+    __shared__ SeedSlots ss;                         // tlog1p0 and tlog1pp only
     lds.load();
     __syncthreads();
+    T* const slot = seed_slots<T>(ss);
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t nfull = n / TILE;
     const size_t off = (size_t)threadIdx.x * EPT;
@@ -156,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_iface(const T* x0, const T* x1, T* z
             vload<NT>(a[1], x0 + tn * TILE + off);
             if constexpr (!DOT) vload<NT>(b[1], x1 + tn * TILE + off);
         }
-        iface_tile<T, VF, EPT>(lds, a[0], b[0], r0, r1);
+        iface_tile<T, VF, EPT>(lds, a[0], b[0], r0, r1, slot);
         vstore<NT>(z0 + t * TILE + off, r0);
         vstore<NT>(z1 + t * TILE + off, r1);
         a[0] = a[1];
@@ -172,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_iface(const T* x0, const T* x1, T* z
             ra.v[e] = i < n ? x0[i] : pad_arg<T>();
             rb.v[e] = (!DOT && i < n) ? x1[i] : T(0);
         }
-        iface_tile<T, VF, EPT>(lds, ra, rb, r0, r1);
+        iface_tile<T, VF, EPT>(lds, ra, rb, r0, r1, slot);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const size_t i = rbase + off + e;

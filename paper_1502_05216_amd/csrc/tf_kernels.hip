@@ -71,85 +71,28 @@ __device__ __forceinline__ void eval_general(const L& lds, T a, T b, bool x1_tin
     else tlog1p_elem<false>(a, b, lds.lt(), lds.mt(), r0, r1);
 }
 
-// Per-wave LDS slots of tlog1p's Newton seeds (up to 4 per lane: 256 binary64
-// values per wave, reused as binary32).
-constexpr int kSeedSlots = 256;
-struct SeedSlots {
-    double v[kBlock / 64][kSeedSlots];
-};
-template <class T> __device__ __forceinline__ T* seed_slots(SeedSlots& ss) {
-    return reinterpret_cast<T*>(ss.v[threadIdx.x / 64]);
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// A fast tlog1p wave's 64 x EPT elements.  The Newton seed of an element is
-// log1p_1x(a0 + a1).  Where that argument equals y0 bit for bit (an inner
-// lane whose y is already renormalised, v0 = y0), the seed is the element's
-// main part x0: both are the 1x log1p of the same value in [-1/2, 1], where
-// its steps do not depend on the SMALL premise.  The other seed arguments (y1
-// beyond half an ulp of y0, and the outer lanes) are packed into the wave's
-// LDS slots by a ballot prefix count and evaluated one per lane, so the wave
-// runs one 1x log1p per 64 such elements instead of one per element slot.
-// The main parts are computed while the packed arguments and the seeds are in
-// flight through LDS.  Every lane of the wave is active (fast waves only).
+// A fast tlog1p wave's 64 x EPT elements: the heads, the seeds shared with the
+// main parts or packed (wave_log1p_seeds), the tails.
 template <class T, int EPT>
 __device__ __forceinline__ void tlog1p_fast_tile(const Vec<T, EPT>& y0, const Vec<T, EPT>& y1,
                                                  Vec<T, EPT>& r0, Vec<T, EPT>& r1, T* slot,
                                                  LogTab<T> lt, Pm1Tab<T> mt) {
-    static_assert(64 * EPT <= kSeedSlots, "seed slots");
-    const int lane = threadIdx.x & 63;
     Tlog1pHead<T> h[EPT];
     bool any_outer[EPT];
-    T arg[EPT];
-    bool need[EPT];
-    int rank[EPT];
-    int total = 0;
+    T arg[EPT], y[EPT], x0[EPT], seed[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         h[e] = tlog1p_fast_head(y0.v[e], y1.v[e], any_outer[e]);
         arg[e] = tlog1p_seed_arg(h[e]);
-        need[e] = P<T>::bits(arg[e]) != P<T>::bits(y0.v[e]);
-        const unsigned long long m = __ballot(need[e]);
-        rank[e] = total + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        total += __popcll(m);
-        if (need[e]) slot[rank[e]] = arg[e];
+        y[e] = y0.v[e];
     }
-    wave_sync();
-    // first pass: lanes 0..63 take the first 64 packed arguments; the main
-    // parts of the first half of the elements run beside it, in the same
-    // basic block, so they cover the LDS latencies
-    constexpr int H = (EPT + 1) / 2;
-    T x0[EPT];
-    T u = slot[lane];
-    u = lane < total ? u : T(0);
-#pragma unroll
-    for (int e = 0; e < H; ++e) x0[e] = log1p_1x<true>(y0.v[e], lt);
-    slot[lane] = log1p_1x<true, true>(u, lt);
-#pragma unroll
-    for (int p = 1; p < EPT; ++p) {
-        if (64 * p < total) {                         // wave-uniform
-            T w = slot[64 * p + lane];
-            w = 64 * p + lane < total ? w : T(0);
-            slot[64 * p + lane] = log1p_1x<true, true>(w, lt);
-        }
-    }
-    wave_sync();
-#pragma unroll
-    for (int e = H; e < EPT; ++e) x0[e] = log1p_1x<true>(y0.v[e], lt);
+    wave_log1p_seeds<T, EPT>(arg, y, x0, seed, slot, lt,
+                             [&](int e) { return log1p_1x<true>(y0.v[e], lt); });
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const T packed = slot[need[e] ? rank[e] : 0];   // unconditional LDS read
-        const T seed = need[e] ? packed : x0[e];
         r0.v[e] = x0[e];
-        r1.v[e] = tlog1p_fast_tail(h[e], x0[e], seed, any_outer[e], mt);
+        r1.v[e] = tlog1p_fast_tail(h[e], x0[e], seed[e], any_outer[e], mt);
     }
-    wave_sync();
 }
 
 // Evaluates a thread's EPT elements.  Returns true when the wave took the fast
