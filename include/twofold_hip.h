@@ -349,6 +349,21 @@ tf_status tf_batch_run_noalloc(const tf_batch_desc* descs, size_t count,
 tf_status tf_set_launch_config(int fn, int dtype, int ept, int blocks_per_cu, int prefetch);
 tf_status tf_get_launch_config(int fn, int dtype, int* ept, int* blocks_per_cu, int* prefetch);
 
+/* Where the twofold-function kernels (tf_texp ... tf_tlog1pf) read their
+ * range-reduction tables: TF_TABLES_AUTO from global memory, read in place,
+ * when an array has at most 8 tiles per compute unit in binary64 or 2 in
+ * binary32 (there the per-workgroup copy to LDS would not pay for itself),
+ * and from that LDS copy otherwise; TF_TABLES_LDS always the LDS copy;
+ * TF_TABLES_GLOBAL always global memory.  The results are the same bit for
+ * bit.  Process-wide setting (tests and tuning), not thread-safe against
+ * concurrent launches; TF_EINVAL for other values.  The default is
+ * TF_TABLES_AUTO. */
+#define TF_TABLES_AUTO 0
+#define TF_TABLES_LDS 1
+#define TF_TABLES_GLOBAL 2
+tf_status tf_set_table_placement(int mode);
+int tf_get_table_placement(void);
+
 /* --- library information ---------------------------------------------- */
 const char* tf_status_string(tf_status s);
 const char* tf_version(void);

@@ -101,6 +101,10 @@ def _open(path):
     lib.tf_set_launch_config.restype = ctypes.c_int
     lib.tf_get_launch_config.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
     lib.tf_get_launch_config.restype = ctypes.c_int
+    lib.tf_set_table_placement.argtypes = [ctypes.c_int]
+    lib.tf_set_table_placement.restype = ctypes.c_int
+    lib.tf_get_table_placement.argtypes = []
+    lib.tf_get_table_placement.restype = ctypes.c_int
     lib.tf_status_string.argtypes = [ctypes.c_int]
     lib.tf_status_string.restype = ctypes.c_char_p
     lib.tf_version.restype = ctypes.c_char_p
@@ -328,3 +332,18 @@ def get_launch_config(fn, dtype):
     _check(_load().tf_get_launch_config(FN_IDS[fn], DTYPE_IDS[dtype], ctypes.byref(e),
                                         ctypes.byref(b), ctypes.byref(p)), "tf_get_launch_config")
     return e.value, b.value, p.value
+
+
+TABLE_PLACEMENTS = {"auto": 0, "lds": 1, "global": 2}
+
+
+def set_table_placement(mode):
+    """Where the twofold-function kernels read their tables: "auto" (global
+    memory for arrays of a few tiles per compute unit, an LDS copy otherwise),
+    "lds" or "global".  Same results bit for bit."""
+    _check(_load().tf_set_table_placement(TABLE_PLACEMENTS[mode]), "tf_set_table_placement")
+
+
+def get_table_placement():
+    v = _load().tf_get_table_placement()
+    return {i: k for k, i in TABLE_PLACEMENTS.items()}[v]

@@ -1,6 +1,6 @@
 // Shared pieces of the library's translation units: the LDS images of the
-// tables, vector loads/stores of a thread's elements, and host-side launch
-// helpers.
+// tables, vector loads/stores of a thread's elements, the packed Newton seeds
+// of the log1p kernels' fast waves, and host-side launch helpers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -79,6 +79,17 @@ template <class T, bool EXP, bool PEXP0, bool PM1, bool LOG> struct Lds {
     }
     __device__ Pm1Tab<T> mt() const { return {CM1}; }
     __device__ LogTab<T> lt() const { return {INVC, LG}; }
+};
+
+// The same accessors over the tables in global memory (read in place, L1/L2
+// hits), for launches where a workgroup has about one tile to evaluate and the
+// LDS copy would be the larger part of its time.
+template <class T> struct GlobalTabs {
+    __device__ void load() {}
+    __device__ ExpTab<T> et() const { return {G<T>::S()}; }
+    __device__ Pexp0Tab<T> pt() const { return {G<T>::E(), G<T>::EK(), G<T>::C()}; }
+    __device__ Pm1Tab<T> mt() const { return {G<T>::CM1()}; }
+    __device__ LogTab<T> lt() const { return {G<T>::INVC(), G<T>::LOG()}; }
 };
 
 template <class T, int FN> struct LdsFor;

@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/twofold_hip.h"
@@ -351,14 +352,19 @@ __device__ __forceinline__ void run_guarded(const L& lds, const T* x0, const T* 
 
 // Plain twofold kernel over one array: workgroups walk the full tiles with a
 // grid stride; the ragged remainder (< one tile) is done by one workgroup.
-template <class T, int FN, int EPT, int PD>
+// GT: the tables are read from global memory (GlobalTabs), for launches of
+// about one tile per workgroup; otherwise each workgroup copies them to LDS.
+template <class T, int FN, int EPT, int PD, bool GT = false>
 __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T* z0, T* z1,
                                                     size_t n) {
-    __shared__ typename LdsFor<T, FN>::type lds;
+    using L = typename std::conditional<GT, GlobalTabs<T>, typename LdsFor<T, FN>::type>::type;
+    __shared__ L lds;
     __shared__ QueueSlots qs;
     __shared__ SeedSlots ss;
-    lds.load();
-    __syncthreads();
+    if constexpr (!GT) {
+        lds.load();
+        __syncthreads();
+    }
     constexpr size_t TILE = (size_t)kBlock * EPT;
     const size_t nfull = n / TILE;
     WaveQueue<T> wq = wave_queue<T>(qs);
@@ -638,6 +644,9 @@ LaunchCfg g_cfg1[4][2] = {
     {{2, 8, 1}, {4, 8, 1}},   // log1p_1x
 };
 
+// Table placement of the twofold-function kernels (tf_set_table_placement).
+std::atomic<int> g_tables{TF_TABLES_AUTO};
+
 template <class T, int FN, int EPT, int PD>
 tf_status launch_twofold_ept(const T* x0, const T* x1, T* z0, T* z1, size_t n, int cus, int bpc,
                              hipStream_t stream) {
@@ -648,6 +657,16 @@ tf_status launch_twofold_ept(const T* x0, const T* x1, T* z0, T* z1, size_t n, i
     size_t tiles = n / tile;
     size_t cap = (size_t)cus * (bpc > 0 ? bpc : occ);
     unsigned grid = (unsigned)(tiles == 0 ? 1 : (tiles < cap ? tiles : cap));
+    // A few tiles per compute unit: the LDS copy of the tables would not pay
+    // for itself, so they are read from global memory (one prefetch stage).
+    // Timed from replayed graphs at 2^17..2^21 elements against the LDS form,
+    // the break-even lies beyond 8 tiles per CU in binary64 (e.g. texp at
+    // 2^19: 5.4 against 6.2 us) and at 2-4 in binary32 (texp at 2^20: 4.7
+    // against 5.2 us with global tables at 4 tiles per CU).
+    const int tm = g_tables.load(std::memory_order_relaxed);
+    if (tm == TF_TABLES_GLOBAL ||
+        (tm == TF_TABLES_AUTO && tiles <= (size_t)cus * (sizeof(T) == 8 ? 8 : 2)))
+        kern = k_twofold<T, FN, EPT, 1, true>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, stream, x0, x1, z0, z1, n);
     return hipGetLastError() == hipSuccess ? TF_OK : TF_ELAUNCH;
 }
@@ -1058,6 +1077,15 @@ tf_status tf_get_launch_config(int fn, int dtype, int* ept, int* blocks_per_cu, 
     *prefetch = c.pd;
     return TF_OK;
 }
+
+tf_status tf_set_table_placement(int mode) {
+    if (mode != TF_TABLES_AUTO && mode != TF_TABLES_LDS && mode != TF_TABLES_GLOBAL)
+        return TF_EINVAL;
+    g_tables.store(mode, std::memory_order_relaxed);
+    return TF_OK;
+}
+
+int tf_get_table_placement(void) { return g_tables.load(std::memory_order_relaxed); }
 
 tf_status tf_batch_plan_create(const tf_batch_desc* descs, size_t count,
                                const tf_batch_config* config, tf_batch_plan** out) {

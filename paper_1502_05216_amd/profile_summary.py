@@ -35,10 +35,12 @@ IFACE_NAMES = ["pexp0", "texp0", "pexpm10", "texpm10", "plog0", "tlog0", "plog1p
 
 def short_name(kernel):
     """Readable name of a kernel from its demangled signature."""
-    m = re.search(r"k_twofold<(double|float), (\d), (\d+), (\d+)>", kernel)
+    m = re.search(r"k_twofold<(double|float), (\d), (\d+), (\d+)(?:, (true|false))?>", kernel)
     if m:
-        return "k_twofold<%s,%s> ept%s pd%s" % (m.group(1), FN_NAMES[int(m.group(2))],
-                                                m.group(3), m.group(4))
+        # "global tables": the instantiation that reads its tables in place
+        return "k_twofold<%s,%s> ept%s pd%s%s" % (m.group(1), FN_NAMES[int(m.group(2))],
+                                                  m.group(3), m.group(4),
+                                                  " global tables" if m.group(5) == "true" else "")
     m = re.search(r"k_iface<(double|float), (\d+), (\d+)>", kernel)
     if m:
         return "k_iface<%s,%s> ept%s" % (m.group(1), IFACE_NAMES[int(m.group(2))], m.group(3))

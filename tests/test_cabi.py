@@ -238,3 +238,21 @@ def test_chain_bwd_argument_validation(lib, name):
         g = [fake] * 4
         g[k] = None
         assert call(2, [1, 3], 10, g=tuple(g)) == 1
+
+
+def test_table_placement_setting(lib):
+    """tf_set_table_placement takes TF_TABLES_AUTO / _LDS / _GLOBAL (0, 1, 2)
+    and rejects anything else with TF_EINVAL, keeping the setting."""
+    from paper_1502_05216_amd import _lib
+    assert lib.tf_get_table_placement() == 0
+    try:
+        for mode, name in ((1, "lds"), (2, "global"), (0, "auto")):
+            assert lib.tf_set_table_placement(mode) == 0
+            assert lib.tf_get_table_placement() == mode
+            assert _lib.get_table_placement() == name
+        assert lib.tf_set_table_placement(2) == 0
+        for bad in (-1, 3, 7):
+            assert lib.tf_set_table_placement(bad) == 1
+            assert lib.tf_get_table_placement() == 2
+    finally:
+        lib.tf_set_table_placement(0)

@@ -33,6 +33,16 @@ def tf():
     yield m
     for (f, d), c in saved.items():
         _lib.set_launch_config(f, d, *c)
+    _lib.set_table_placement("auto")
+
+
+@pytest.fixture(autouse=True)
+def auto_tables():
+    """Every test leaves the table placement automatic."""
+    yield
+    from paper_1502_05216_amd import _lib
+    if _lib._lib is not None:
+        _lib.set_table_placement("auto")
 
 
 def gpu_call(tf, fn, x0, x1):
@@ -42,15 +52,17 @@ def gpu_call(tf, fn, x0, x1):
     return g0.cpu().numpy(), g1.cpu().numpy()
 
 
+@pytest.mark.parametrize("tables", ["lds", "global"])
 @pytest.mark.parametrize("ept", [0, 1, 4], ids=["default", "ept1", "ept4"])
 @pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
 @pytest.mark.parametrize("fn", FUNCS)
-def test_fast_and_general_bodies_agree(tf, fn, dt, ept):
+def test_fast_and_general_bodies_agree(tf, fn, dt, ept, tables):
     from paper_1502_05216_amd import _lib
     dts = "f64" if dt == np.float64 else "f32"
     if ept:
         _, bpc, pd = _lib.get_launch_config(fn, dts)
         _lib.set_launch_config(fn, dts, ept, bpc, pd)
+    _lib.set_table_placement(tables)
     n = 256 * 4 * 40 + 77
     x0, x1 = workloads.twofold_inputs(fn, n, dt, seed=91, edges=0.0)
     # signed zero second parts: the fast renormalisation of the logs must give

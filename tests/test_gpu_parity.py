@@ -196,3 +196,31 @@ def test_log1p_tiny_arguments(tf, dt):
     torch.cuda.synchronize()
     p0, p1 = getattr(oracle, "tlog1p0" + sfx(dt))(x)
     compare(h0.cpu().numpy(), h1.cpu().numpy(), p0, p1, "tlog1p0 tiny %s" % np.dtype(dt).name)
+
+
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+@pytest.mark.parametrize("fn", FUNCS)
+def test_table_placement_same_bits(tf, fn, dt):
+    """The twofold kernels read their tables from an LDS copy or in place from
+    global memory (automatically by size); both placements, forced, give the
+    same bits at sizes from one element to several tiles per compute unit and
+    at the size where the automatic choice switches, and meet the oracle."""
+    from paper_1502_05216_amd import _lib
+    per_cu = 8 if dt == np.float64 else 2
+    ept = _lib.get_launch_config(fn, "f64" if dt == np.float64 else "f32")[0]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    switch = cus * per_cu * 256 * ept
+    try:
+        for n in (1, 700, 65536 + 3, switch, switch + 256 * ept, 3 * switch + 11):
+            x0, x1 = workloads.twofold_inputs(fn, n, dt, seed=n % 977, edges=0.01)
+            print("case placement", fn, np.dtype(dt).name, n, flush=True)
+            res = {}
+            for mode in ("lds", "global"):
+                _lib.set_table_placement(mode)
+                res[mode] = gpu_call(tf, fn, x0, x1)
+            for k in (0, 1):
+                assert same_bits(res["lds"][k], res["global"][k]).all(), (fn, n, k)
+            o0, o1 = getattr(oracle, fn + sfx(dt))(x0, x1, threads=8)
+            compare(res["lds"][0], res["lds"][1], o0, o1, "%s n=%d placement" % (fn, n))
+    finally:
+        _lib.set_table_placement("auto")
