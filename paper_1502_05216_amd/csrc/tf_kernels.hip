@@ -352,8 +352,8 @@ __device__ __forceinline__ void run_guarded(const L& lds, const T* x0, const T* 
 
 // Plain twofold kernel over one array: workgroups walk the full tiles with a
 // grid stride; the ragged remainder (< one tile) is done by one workgroup.
-// GT: the tables are read from global memory (GlobalTabs), for launches of
-// about one tile per workgroup; otherwise each workgroup copies them to LDS.
+// GT: the tables are read from global memory (GlobalTabs), for arrays of a few
+// tiles per compute unit; otherwise each workgroup copies them to LDS.
 template <class T, int FN, int EPT, int PD, bool GT = false>
 __global__ __launch_bounds__(kBlock) void k_twofold(const T* x0, const T* x1, T* z0, T* z1,
                                                     size_t n) {
