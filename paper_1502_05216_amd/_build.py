@@ -57,9 +57,13 @@ def _run(cmd, verbose):
 #             rebalancing of table size against Horner length that the section
 #             "Function pexp0()" closes with; validated against the binary128
 #             etalon, not the oracle (whose parameters are the paper's)
+#   accexp:   texp's second part with the product z0 t1 taken exactly for a
+#             coupled x1 and its low part carried apart (pexp renormalises
+#             it); validated against the binary128 etalon, not the oracle
 VARIANTS = {
     "horner2x": ["-DTF_HORNER_1X_TAIL=0"],
     "k6": ["-DTF_PEXP0_K=6"],
+    "accexp": ["-DTF_TEXP_ACC=1"],
 }
 
 

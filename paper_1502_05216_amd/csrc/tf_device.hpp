@@ -516,21 +516,68 @@ template <class T> __device__ __forceinline__ bool tlog1p_fast_arg(T y0, T y1) {
            fabs_(y1) <= fabs_(y0);
 }
 
+// Build define TF_TEXP_ACC=1 (the flagged variant "accexp"): texp's second
+// part in twofold.  The method's step (section "Twofold exponent", algorithm
+// texp, step 4) forms z0 t1 + (v1 + (v0 - z0)) with one rounded product of the
+// 1x main part z0 and t1 = expm1(x1): it drops (v - z0) t1, about an ulp of z0
+// times t1, and rounds the product, each near 2^-97 of the result for a
+// coupled x1 at |x0| ~ 700.  The variant takes e^x0 (1 + t1) - z0 as
+// v0 t1 (an exact FMA product) + v1 t1 + (v1 + (v0 - z0)), with t1 = x1 +
+// x1^2/2 for a tiny x1 (far below its ulp there), and keeps the low part of
+// the sum apart: the t-function texp adds it in one rounding, the coupled
+// pexp carries it through its renormalisation.  The default keeps the
+// method's step.
+#ifndef TF_TEXP_ACC
+#define TF_TEXP_ACC 0
+#endif
+constexpr bool kTexpAcc = TF_TEXP_ACC != 0;
+
+// texp's second part in the 2^-k domain, from z0s = z0 2^-k, t1 = expm1(x1),
+// x1 and v = pexp0(x0) 2^-k (one element): hi + lo.  The default gives
+// z0s t1 + (v1 + (v0 - z0s)) as hi with lo = 0.  tiny: |x1| < EXPM1_TINY.
+template <class T> struct SecondPart { T hi, lo; };
+template <class T>
+__device__ __forceinline__ SecondPart<T> texp_second(T z0s, T t1, T x1, bool tiny, Tw<T> v) {
+    const T rest = v.x1 + (v.x0 - z0s);
+    if constexpr (kTexpAcc) {
+        const T tt = tiny ? x1 : t1;
+        Tw<T> p = two_prod(v.x0, tt);
+        const T q = tiny ? v.x0 * (x1 * x1 * T(0.5)) : T(0);
+        // a non-finite product (x1 infinite or NaN) keeps the default's value
+        if (!(fabs_(p.x0) < P<T>::INF)) return {z0s * t1 + rest, T(0)};
+        return {p.x0, (p.x1 + (v.x1 * tt + q)) + rest};
+    } else {
+        return {z0s * t1 + rest, T(0)};
+    }
+}
+
 // texp.  FAST: texp_fast_arg (then z0 is finite and pexp0 is in range).
 // TAIL: pexp0 with the 1x Horner tail (z1 takes pexp0's value, not its
-// representation, up to its own last bits).
+// representation, up to its own last bits).  z2o (the variant's low part of
+// the second part, for the coupled pexp): if given, z1o is the high part and
+// *z2o the low one (0 in the default build); otherwise z1o is their sum.
 template <bool FAST, bool TAIL, class T>
 __device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et, Pexp0Tab<T> pt,
-                                          T& z0o, T& z1o) {
+                                          T& z0o, T& z1o, T* z2o = nullptr) {
     using K = P<T>;
     if constexpr (FAST) {
         T z0 = exp1x<true>(x0, et);
         T t1 = expm1_tiny(x1);
         Scaled<T> s = pexp0_core<true, TAIL>(x0, pt);
         T z0s = fldexp(z0, -s.k);                     // exact
-        T z1s = z0s * t1 + (s.v.x1 + (s.v.x0 - z0s));
+        SecondPart<T> zs = texp_second(z0s, t1, x1, true, s.v);
         z0o = z0;
-        z1o = fldexp(z1s, s.k);
+        if constexpr (kTexpAcc) {
+            if (z2o) {
+                z1o = fldexp(zs.hi, s.k);
+                *z2o = fldexp(zs.lo, s.k);
+            } else {
+                z1o = fldexp(zs.hi + zs.lo, s.k);
+            }
+        } else {
+            z1o = fldexp(zs.hi, s.k);
+            if (z2o) *z2o = T(0);
+        }
     } else {
         T z0 = exp1x<false>(x0, et);
         T t1 = expm1_of_x1(x1, x1_tiny, et);
@@ -542,9 +589,19 @@ __device__ __forceinline__ void texp_elem(T x0, T x1, bool x1_tiny, ExpTab<T> et
         T v1 = in ? s.v.x1 : T(0);
         int k = in ? s.k : 0;
         T z0s = fldexp(z0, -k);                       // exact
-        T z1s = z0s * t1 + (v1 + (v0 - z0s));
+        SecondPart<T> zs = texp_second(z0s, t1, x1, fabs_(x1) < K::EXPM1_TINY, Tw<T>{v0, v1});
         z0o = z0;
-        z1o = special_rule(z0, fldexp(z1s, k));
+        if constexpr (kTexpAcc) {
+            if (z2o) {
+                z1o = special_rule(z0, fldexp(zs.hi, k));
+                *z2o = special_rule(z0, fldexp(zs.lo, k));
+            } else {
+                z1o = special_rule(z0, fldexp(zs.hi + zs.lo, k));
+            }
+        } else {
+            z1o = special_rule(z0, fldexp(zs.hi, k));
+            if (z2o) *z2o = T(0);
+        }
     }
 }
 
@@ -833,6 +890,19 @@ template <class T> __device__ __forceinline__ void renorm_out(T z0, T z1, T& z0o
     Tw<T> r = fast_two_sum(z0, z1);
     T o0 = fin ? r.x0 : z0;
     T o1 = fin ? r.x1 : z1;
+    z0o = o0;
+    z1o = special_rule(o0, o1);
+}
+
+// The renormalised z0 + z1 + z2 (|z2| << |z1| << |z0|, z0 finite) as a coupled
+// pair; non-finite z0 as renorm_out.
+template <class T>
+__device__ __forceinline__ void renorm_out3(T z0, T z1, T z2, T& z0o, T& z1o) {
+    const bool fin = !(isnan_(z0) || fabs_(z0) == P<T>::INF);
+    Tw<T> r = fast_two_sum(z0, z1);
+    Tw<T> q = fast_two_sum(r.x0, r.x1 + z2);
+    T o0 = fin ? q.x0 : z0;
+    T o1 = fin ? q.x1 : z1;
     z0o = o0;
     z1o = special_rule(o0, o1);
 }

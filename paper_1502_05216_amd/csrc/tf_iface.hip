@@ -86,9 +86,10 @@ __device__ __forceinline__ void eval_iface(const L& lds, T a, T b, bool x1_tiny,
     } else if constexpr (VF == V_TLOG1P0) {
         log_iface_elem<LK_LOG1P0, false, FAST>(a, T(0), lds.lt(), lds.mt(), r0, r1);
     } else if constexpr (VF == V_PEXP) {
-        T z0, z1;
-        texp_elem<FAST, false>(a, b, FAST || x1_tiny, lds.et(), lds.pt(), z0, z1);
-        renorm_out(z0, z1, r0, r1);
+        T z0, z1, z2;
+        texp_elem<FAST, false>(a, b, FAST || x1_tiny, lds.et(), lds.pt(), z0, z1, &z2);
+        if constexpr (kTexpAcc) renorm_out3(z0, z1, z2, r0, r1);
+        else renorm_out(z0, z1, r0, r1);
     } else if constexpr (VF == V_PEXPM1) {
         T z0, z1;
         if constexpr (FAST) (void)texpm1_small_fast(a, b, lds.et(), lds.mt(), z0, z1);

@@ -1258,6 +1258,8 @@ const char* tf_status_string(tf_status s) {
 const char* tf_version(void) {
 #if TF_HORNER_1X_TAIL && TF_PEXP0_K == 6
     return "twofold_hip 0.2 (gfx950; Horner with 1x tails; pexp0 K=6)";
+#elif TF_HORNER_1X_TAIL && TF_TEXP_ACC
+    return "twofold_hip 0.2 (gfx950; Horner with 1x tails; texp exact z0 t1)";
 #elif TF_HORNER_1X_TAIL
     return "twofold_hip 0.2 (gfx950; Horner with 1x tails)";
 #else
