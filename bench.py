@@ -460,7 +460,7 @@ def main():
             x0 = torch.from_numpy(a).to(dev)
             x1 = torch.from_numpy(b).to(dev)
             o = (torch.empty_like(x0), torch.empty_like(x0))
-            ms = kernel_ms(lambda: getattr(tf, fn)(x0, x1, out=o), (), 10)
+            ms = kernel_ms(lambda: getattr(tf, fn)(x0, x1, out=o), (), 20, warm=10, windows=4)
             ops_s = N * opc["f32"][fn]["ops"] / (ms * 1e-3)
             per32[fn] = {"ms": ms, "gelem_s": N / ms / 1e6,
                          "fp32_tflops": N * opc["f32"][fn]["flops"] / ms / 1e9,
