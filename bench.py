@@ -19,6 +19,7 @@ the host cores over the step's arrays.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-f32]
                     [--no-batch] [--no-chain] [--no-interface] [--no-arith]
+                    [--variant horner2x|k6|accexp]
 """
 import argparse
 import json
