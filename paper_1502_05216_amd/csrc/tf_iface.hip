@@ -12,9 +12,9 @@
 // x1) -> z0, z1 once, with the element functions of tf_device.hpp: a wave
 // whose lanes all hold an ordinary argument takes the FAST form, any other
 // wave the general form (tlog1p0 and tlog1pp share their Newton seeds with the
-// main parts on fast waves, as tlog1p does).  There is no deferred-lane queue here: on the waves
-// of pexpm10 / texpm10 / pexpm1 that hold a lane with |x0| > ln 2 every lane
-// runs pexp0 - 1 as well.
+// main parts on fast waves, as tlog1p does).  There is no deferred-lane queue
+// here: on the waves of pexpm10 / texpm10 / pexpm1 that hold a lane with
+// |x0| > ln 2 every lane runs pexp0 - 1 as well.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
