@@ -96,6 +96,18 @@ def traffic_for(kernel, n_elem):
 PAPER_MOPS_PER_CORE = {"texp": 11.86, "texpm1": 12.28, "tlog": 7.00, "tlog1p": 7.06}
 
 
+def host_cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(inputs64, min_seconds, core_sample):
     """The oracle on the host: whole passes over the step's binary64 arrays on
     up to 16 threads until min_seconds have passed, plus a one-thread rate per
@@ -135,7 +147,7 @@ def cpu_baseline(inputs64, min_seconds, core_sample):
             "kind": "oracle",
             "sample": "%d whole pass(es) over the step's 4 binary64 arrays of %d elements, "
                       "scalar oracle, OpenMP static schedule" % (passes, n),
-            "seconds": t, "host_cpus": os.cpu_count(),
+            "seconds": t, "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model(),
             "one_thread": {"sample": core_sample, "per_function": per_core},
             "context_one_thread": context}
 
