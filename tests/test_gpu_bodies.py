@@ -92,9 +92,10 @@ def test_fast_and_general_bodies_agree(tf, fn, dt, ept, tables):
         assert (np.abs(x0) > 0.7).sum() > 100
 
 
+@pytest.mark.parametrize("tables", ["lds", "global"])
 @pytest.mark.parametrize("frac", [1.0, 0.5], ids=["all", "half"])
 @pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
-def test_texpm1_deferred_lanes_against_oracle(tf, dt, frac):
+def test_texpm1_deferred_lanes_against_oracle(tf, dt, frac, tables):
     """texpm1 where every lane (or every other one) has |x0| > ln 2, so the
     wave queue fills on every tile and the drain rewrites the z1 of most
     lines: the result must still meet the parity bar everywhere."""
@@ -109,7 +110,9 @@ def test_texpm1_deferred_lanes_against_oracle(tf, dt, frac):
     small = rng.uniform(-0.69, 0.69, n)
     x0 = np.where(rng.random(n) < frac, big, small).astype(dt)
     x1 = (x0 * rng.uniform(-1, 1, n).astype(dt) * np.finfo(dt).eps).astype(dt)
-    print("case texpm1", dts, "deferred fraction", frac, flush=True)
+    from paper_1502_05216_amd import _lib
+    _lib.set_table_placement(tables)
+    print("case texpm1", dts, "deferred fraction", frac, "tables", tables, flush=True)
     g0, g1 = gpu_call(tf, "texpm1", x0, x1)
     o0, o1 = getattr(oracle, "texpm1" + ("" if dt == np.float64 else "f"))(x0, x1)
     compare(g0, g1, o0, o1, "texpm1 %s deferred %.1f" % (dts, frac))
@@ -156,10 +159,11 @@ def _branch_point_args(fn, dt, n, seed):
     return x0, x1
 
 
+@pytest.mark.parametrize("tables", ["lds", "global"])
 @pytest.mark.parametrize("ept", [0, 1, 4], ids=["default", "ept1", "ept4"])
 @pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
 @pytest.mark.parametrize("fn", ["tlog", "tlog1p"])
-def test_fast_body_at_branch_points(tf, fn, dt, ept):
+def test_fast_body_at_branch_points(tf, fn, dt, ept, tables):
     """Whole waves of ordinary arguments at the logs' branch points run the
     fast body (its cheaper Newton sum, outer-branch sums and + n ln2); with
     one NaN second part in every 64 elements the same arguments run the
@@ -173,7 +177,8 @@ def test_fast_body_at_branch_points(tf, fn, dt, ept):
         _lib.set_launch_config(fn, dts, ept, bpc, pd)
     n = 256 * 4 * 24
     x0, x1 = _branch_point_args(fn, dt, n, seed=95)
-    print("case branch points", fn, dts, "ept", ept or "default", flush=True)
+    _lib.set_table_placement(tables)
+    print("case branch points", fn, dts, "ept", ept or "default", tables, flush=True)
     a0, a1 = gpu_call(tf, fn, x0, x1)
     o0, o1 = getattr(oracle, fn + ("" if dt == np.float64 else "f"))(x0, x1)
     compare(a0, a1, o0, o1, "%s %s branch points (fast body)" % (fn, dts))
@@ -188,10 +193,11 @@ def test_fast_body_at_branch_points(tf, fn, dt, ept):
             fn, dts, name, (~ok).sum())
 
 
+@pytest.mark.parametrize("tables", ["lds", "global"])
 @pytest.mark.parametrize("mix", ["none", "quarter", "half", "all"])
 @pytest.mark.parametrize("ept", [1, 2, 4])
 @pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
-def test_tlog1p_shared_seeds(tf, dt, ept, mix):
+def test_tlog1p_shared_seeds(tf, dt, ept, mix, tables):
     """tlog1p's fast waves take the Newton seed of an element from its main
     part when the seed's argument equals y0, and evaluate the other seeds
     packed 64 to a pass.  Waves where no element, a quarter, half or every
@@ -204,6 +210,7 @@ def test_tlog1p_shared_seeds(tf, dt, ept, mix):
     dts = "f64" if dt == np.float64 else "f32"
     _, bpc, pd = _lib.get_launch_config("tlog1p", dts)
     _lib.set_launch_config("tlog1p", dts, ept, bpc, pd)
+    _lib.set_table_placement(tables)
     n = 256 * 4 * 20
     rng = np.random.default_rng(96 + ept)
     p = {"none": 0.0, "quarter": 0.25, "half": 0.5, "all": 1.0}[mix]
@@ -215,7 +222,7 @@ def test_tlog1p_shared_seeds(tf, dt, ept, mix):
     x1[outer] = (x0[outer] * dt(np.finfo(dt).eps / 4)).astype(dt)
     loose = need & ~outer                                         # inner, y1 > ulp(y0)/2
     x1[loose] = (np.spacing(np.abs(x0[loose])) * dt(0.75)).astype(dt)
-    print("case tlog1p shared seeds", dts, "ept", ept, mix, flush=True)
+    print("case tlog1p shared seeds", dts, "ept", ept, mix, tables, flush=True)
     a0, a1 = gpu_call(tf, "tlog1p", x0, x1)
     o0, o1 = getattr(oracle, "tlog1p" + ("" if dt == np.float64 else "f"))(x0, x1)
     compare(a0, a1, o0, o1, "tlog1p %s shared seeds ept %d %s" % (dts, ept, mix))
