@@ -141,3 +141,33 @@ def test_fast_and_general_bodies_agree(tf, name, dt):
         ok = same_bits(a[keep], b[keep])
         assert ok.all(), "%s %s: %s differs at %d elements" % (name, np.dtype(dt).name, part,
                                                                (~ok).sum())
+
+
+@pytest.mark.parametrize("dt", DTS, ids=["f64", "f32"])
+@pytest.mark.parametrize("name", ["tlog1pp", "plog1p"])
+def test_log1p_coupled_with_loose_second_parts(tf, name, dt):
+    """The coupled log1p functions on arguments that are not coupled but still
+    take the fast body (|y1| up to 2^-30 |y0|, binary32 2^-26): on tlog1pp's
+    fast waves the Newton seed then differs from the main part on every inner
+    lane and is evaluated packed.  Fast against general body bit for bit (one
+    NaN second part in every 64 elements), and against the oracle."""
+    from parity_util import same_bits
+    n = 256 * 4 * 16 + 45
+    rng = np.random.default_rng(221)
+    x0 = rng.uniform(-0.6, 1.2, n).astype(dt)
+    x0[x0 <= -0.99] = dt(0.25)
+    rel = 2.0 ** (-30 if dt == np.float64 else -26)
+    x1 = (x0 * rng.uniform(-1, 1, n) * rel).astype(dt)
+    print("case loose", name, np.dtype(dt).name, flush=True)
+    a0, a1 = on_gpu(tf, name, x0, x1)
+    o0, o1 = on_oracle(name, dt, x0, x1)
+    compare(a0, a1, o0, o1, "%s %s loose second parts" % (name, np.dtype(dt).name))
+    p1 = x1.copy()
+    p1[::64] = np.nan
+    b0, b1 = on_gpu(tf, name, x0, p1)
+    keep = np.ones(n, bool)
+    keep[::64] = False
+    for part, a, b in (("z0", a0, b0), ("z1", a1, b1)):
+        ok = same_bits(a[keep], b[keep])
+        assert ok.all(), "%s %s: %s differs at %d elements" % (name, np.dtype(dt).name, part,
+                                                               (~ok).sum())
