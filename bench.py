@@ -350,9 +350,15 @@ def bench_chain(tf, workloads, reps):
         tf.texp_bwd(*a, *d, out=(buf[10], buf[11]))
     ms = kernel_ms(fwd_bwd, (), reps)
     ms_stage = kernel_ms(fwd_bwd_stagewise, (), reps)
+    # elements whose texpm1 stage overflows (x0 above ln ln DBL_MAX: y = inf
+    # and a NaN gradient), counted apart as the chain's workload states
+    fwd_bwd()
+    overflow = int((~torch.isfinite(buf[4])).sum())
+    nan_grad = int((~torch.isfinite(buf[10])).sum())
     del arrs, buf
     torch.cuda.empty_cache()
     return {"n": n, "ms": ms, "gelem_s": n / ms / 1e6,
+            "overflow_elements": overflow, "nonfinite_gradients": nan_grad,
             "launches": 4, "hbm_bytes_per_elem": 3 * 32 + 64,
             "stagewise_backward": {"ms": ms_stage, "gelem_s": n / ms_stage / 1e6,
                                    "launches": 6, "hbm_bytes_per_elem": 3 * 32 + 3 * 48}}
@@ -503,8 +509,10 @@ def main():
     if not args.no_chain:
         log("forward+backward chain, 2^24")
         chain = bench_chain(tf, workloads, 10)
-        log("chain %.3f ms  %.1f Gelem/s (single-stage backward launches %.3f ms)"
-            % (chain["ms"], chain["gelem_s"], chain["stagewise_backward"]["ms"]))
+        log("chain %.3f ms  %.1f Gelem/s (single-stage backward launches %.3f ms); "
+            "%d of %d elements overflow at texpm1" % (chain["ms"], chain["gelem_s"],
+                                                      chain["stagewise_backward"]["ms"],
+                                                      chain["overflow_elements"], chain["n"]))
 
     iface = None
     if not args.no_interface:
